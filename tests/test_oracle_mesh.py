@@ -1,0 +1,228 @@
+"""Pins of the oracle's mesh operators: CIC, FFT conventions, force, P(k)."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import mesh as M
+from oracle import pm
+from synthetic import uniform, normal
+
+
+def brute_dft3(x):
+    """O(N^6) forward DFT, exp(-2 pi i n.j / N), written out directly."""
+    n = x.shape[0]
+    j = np.arange(n)
+    E = np.exp(-2j * np.pi * np.outer(j, j) / n)
+    out = np.zeros((n, n, n), dtype=complex)
+    for a, b, c in itertools.product(range(n), repeat=3):
+        out[a, b, c] = np.sum(x * E[a][:, None, None] * E[b][None, :, None]
+                              * E[c][None, None, :])
+    return out
+
+
+@pytest.mark.parametrize("n", [4, 8])
+def test_rfft_matches_brute_force_dft(n):
+    x = normal((n, n, n), 11)
+    ref = brute_dft3(x)
+    got = M.rfftn(x)
+    np.testing.assert_allclose(got, ref[:, :, :n // 2 + 1], rtol=0, atol=1e-12 * np.abs(ref).max())
+    back = M.irfftn(got, n)
+    np.testing.assert_allclose(back, x, atol=1e-13)
+
+
+def test_rfft_16_matches_matrix_dft():
+    # separable matrix DFT along each axis (a different route than FFT)
+    n = 16
+    x = normal((n, n, n), 12)
+    j = np.arange(n)
+    E = np.exp(-2j * np.pi * np.outer(j, j) / n)
+    ref = np.einsum("ai,bj,ck,ijk->abc", E, E, E, x)
+    np.testing.assert_allclose(M.rfftn(x), ref[:, :, :n // 2 + 1], atol=1e-11)
+
+
+def test_wave_integer_layout():
+    n0, n1, n2 = M.wave_integers(8)
+    assert list(n0.ravel()) == [0, 1, 2, 3, -4, -3, -2, -1]
+    assert list(n2.ravel()) == [0, 1, 2, 3, 4]
+
+
+# ----------------------------------------------------------- CIC
+
+def test_mass_conservation():
+    mesh, box = 16, 32.0
+    x = uniform((1000, 3), 1, -box, 2 * box)    # includes wrap-around
+    v = uniform(1000, 2, 0.5, 2.0)
+    rho = M.scatter(x, mesh, box, v)
+    assert abs(rho.sum() - v.sum()) < 1e-12 * v.sum()
+
+
+def test_particle_on_node_deposits_into_one_cell():
+    mesh, box = 8, 8.0
+    x = np.array([[2.5, 3.5, 7.5]])       # cell centres at (i + 1/2)
+    rho = M.scatter(x, mesh, box, np.ones(1))
+    assert rho[2, 3, 7] == 1.0 and np.count_nonzero(rho) == 1
+
+
+def test_integer_cell_shift_shifts_density():
+    mesh, box = 16, 16.0
+    x = uniform((300, 3), 3, 0, box)
+    r0 = M.scatter(x, mesh, box, np.ones(300))
+    r1 = M.scatter(x + np.array([1.0, 2.0, -3.0]), mesh, box, np.ones(300))
+    np.testing.assert_allclose(np.roll(r0, (1, 2, -3), axis=(0, 1, 2)), r1, atol=1e-12)
+
+
+def test_scatter_gather_transpose():
+    mesh, box = 16, 20.0
+    x = uniform((500, 3), 4, 0, box)
+    v = normal(500, 5)
+    g = normal((mesh,) * 3, 6)
+    lhs = np.sum(M.scatter(x, mesh, box, v) * g)
+    rhs = np.sum(v * M.gather(g, x, box))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_gather_grad_matches_finite_difference():
+    mesh, box = 16, 16.0
+    x = uniform((200, 3), 7, 0, box)
+    # keep particles away from node planes (the weight derivative jumps there)
+    u = x * mesh / box - 0.5
+    frac = u - np.floor(u)
+    x = x[np.all((frac > 0.01) & (frac < 0.99), axis=1)]
+    g = normal((mesh,) * 3, 8)
+    an = M.gather_grad(g, x, box)
+    h = 1e-6
+    for ax in range(3):
+        e = np.zeros(3)
+        e[ax] = h
+        fd = (M.gather(g, x + e, box) - M.gather(g, x - e, box)) / (2 * h)
+        np.testing.assert_allclose(an[:, ax], fd, rtol=1e-7, atol=1e-8)
+
+
+@pytest.mark.parametrize("ratio", [1, 2])
+def test_unperturbed_lattice_is_uniform(ratio):
+    np_, mesh = 8, 8 * ratio
+    box = 16.0
+    q = pm.lattice(np_, box)
+    delta = M.density(q, mesh, box, np_ ** 3)
+    assert np.max(np.abs(delta)) < 1e-13
+    st = pm.Setup(np_, mesh, box, 1, None)
+    F, _, _ = pm.pm_force(q, st)
+    assert np.max(np.abs(F)) < 1e-13
+
+
+# ----------------------------------------------------------- force
+
+def test_single_mode_force_is_spectrally_exact():
+    mesh, box = 16, 32.0
+    n = np.array([1, 2, 3])
+    c = (np.arange(mesh) + 0.5) * box / mesh
+    X = np.stack(np.meshgrid(c, c, c, indexing="ij"), axis=-1)
+    k = 2 * np.pi * n / box
+    phase = X @ k
+    delta = np.cos(phase)
+    F, _ = M.force_meshes(delta, box)
+    k2 = k @ k
+    for j in range(3):
+        np.testing.assert_allclose(F[j], -k[j] * np.sin(phase) / k2, atol=1e-12)
+
+
+def test_force_sums_to_zero_and_no_self_force():
+    st = pm.Setup(8, 16, 16.0, 1, None)
+    x = uniform((512, 3), 9, 0, 16.0)
+    F, _, _ = pm.pm_force(x, st)
+    assert np.max(np.abs(F.sum(axis=0))) < 1e-10 * np.abs(F).sum()
+    # one particle alone feels no force
+    F1, _, _ = pm.pm_force(np.array([[3.3, 7.1, 0.4]]), pm.Setup(1, 16, 16.0, 1, None))
+    assert np.max(np.abs(F1)) < 1e-12
+
+
+def test_two_particle_force_against_inverse_square():
+    """A probe's PM force from one mass vs M/(4 pi r^2) minus the uniform
+    background term M r/(3 L^3); orientation-averaged within 2% for
+    4 cells <= r <= L/8 (the periodic images add only O(r^3) there)."""
+    mesh, box = 128, 128.0
+    st = pm.Setup(1, mesh, box, 1, None)
+    src = np.array([[40.3, 61.7, 50.2]])
+    delta = M.density(src, mesh, box, 1)
+    F, _ = M.force_meshes(delta, box)
+    Mass = box ** 3
+    dirs = normal((64, 3), 13)
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    for r in (4.0, 8.0, 16.0):
+        x = src + r * dirs
+        f = np.stack([M.gather(F[j], x, box) for j in range(3)], axis=1)
+        radial = -np.sum(f * dirs, axis=1)      # attraction toward the source
+        expect = Mass / (4 * np.pi * r * r) - Mass * r / (3 * box ** 3)
+        ratio = radial.mean() / expect
+        assert abs(ratio - 1) < 0.02, (r, ratio)
+
+
+def test_force_transpose_dot_product():
+    mesh, box = 16, 24.0
+    filt = uniform(3 * (mesh // 2) ** 2 + 1, 14, 0.5, 1.5)
+    d = normal((mesh,) * 3, 15)
+    G = [normal((mesh,) * 3, 16 + j) for j in range(3)]
+    F, _ = M.force_meshes(d, box, filt)
+    lhs = sum(np.sum(f * g) for f, g in zip(F, G))
+    back, _ = M.force_transpose(G, box, filt)
+    rhs = np.sum(d * back)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_force_vjp_dot_product_and_fd():
+    st = pm.Setup(4, 8, 8.0, 1, None)
+    x = uniform((64, 3), 20, 0, 8.0)
+    v = normal((64, 3), 21)
+    d = normal((64, 3), 22)
+    xi, _, _ = pm.pm_force_vjp(x, v, st)
+    h = 1e-7
+    fp, _, _ = pm.pm_force(x + h * d, st)
+    fm, _, _ = pm.pm_force(x - h * d, st)
+    fd = np.sum(v * (fp - fm)) / (2 * h)
+    assert abs(fd - np.sum(xi * d)) < 1e-6 * abs(fd)
+
+
+def test_filter_cotangent_matches_finite_difference():
+    st = pm.Setup(4, 8, 8.0, 1, None)
+    x = uniform((64, 3), 23, 0, 8.0)
+    v = normal((64, 3), 24)
+    nt = 3 * 16 + 1
+    filt = uniform(nt, 25, 0.8, 1.2)
+    _, fbar, _ = pm.pm_force_vjp(x, v, st, filt)
+    d = normal(nt, 26)
+    h = 1e-6
+    fp, _, _ = pm.pm_force(x, st, filt + h * d)
+    fm, _, _ = pm.pm_force(x, st, filt - h * d)
+    fd = np.sum(v * (fp - fm)) / (2 * h)
+    assert abs(fd - np.dot(fbar, d)) < 1e-8 * max(1, abs(fd))
+
+
+# ----------------------------------------------------------- P(k)
+
+def test_power_spectrum_single_mode():
+    mesh, box, A = 32, 64.0, 0.7
+    c = (np.arange(mesh) + 0.5) * box / mesh
+    X = np.stack(np.meshgrid(c, c, c, indexing="ij"), axis=-1)
+    n = np.array([3, 0, 4])                     # |n| = 5 exactly
+    delta = A * np.cos(X @ (2 * np.pi * n / box))
+    k, P, N = M.power_spectrum(delta, box)
+    nonzero = np.flatnonzero(P > 1e-20)
+    assert list(nonzero) == [4]                  # shell b = 5
+    expect = box ** 3 / mesh ** 6 * (A * mesh ** 3 / 2) ** 2 * 2 / N[4]
+    assert abs(P[4] / expect - 1) < 1e-12
+
+
+def test_power_spectrum_parseval_and_counts():
+    mesh, box = 16, 16.0
+    d = normal((mesh,) * 3, 30)
+    d -= d.mean()
+    dk = M.rfftn(d)
+    w = M.half_spectrum_weights(mesh)
+    assert abs(np.sum(w * np.abs(dk) ** 2) / mesh ** 3 / np.sum(d * d) - 1) < 1e-12
+    k, P, N = M.power_spectrum(d, box, n_bins=20)
+    # every mode with 1 <= round(|n|) <= 20 counted once in the full spectrum
+    n = np.fft.fftfreq(mesh, 1 / mesh)
+    nn = np.sqrt(n[:, None, None] ** 2 + n[None, :, None] ** 2 + n[None, None, :] ** 2)
+    b = np.floor(nn + 0.5)
+    assert N.sum() == np.sum((b >= 1) & (b <= 20))

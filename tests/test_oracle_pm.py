@@ -1,0 +1,188 @@
+"""Pins of the oracle's simulation, adjoint and gradients.
+
+Plane-wave linear growth, IC statistics, FP64 reversibility, dot-product tests
+of the whole discrete step, and central finite differences of every gradient.
+"""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle import cosmology as C
+from oracle import mesh as M
+from oracle import mlp
+from oracle import pm
+from synthetic import Cosmology, Workload, mlp_init, normal, white_noise
+
+CO = Cosmology()
+
+
+def tiny(n_steps=3, np_=8, mesh=16, box=32.0):
+    return pm.Setup(np_, mesh, box, n_steps, CO)
+
+
+# ------------------------------------------------------------ ICs
+
+def test_ic_mode_amplitudes():
+    np_, box = 16, 64.0
+    noise = white_noise(np_, 1)
+    radial = pm.ic_radial(np_, box, CO)
+    s = pm.zeldovich_displacement(noise, box, radial)
+    # divergence of s equals minus the coloured noise (off the Nyquist planes)
+    wk = M.rfftn(noise)
+    n0, n1, n2 = M.wave_integers(np_)
+    kf = 2 * np.pi / box
+    div = sum(1j * kf * nj * M.rfftn(s[:, j].reshape(np_, np_, np_))
+              for j, nj in enumerate((n0, n1, n2)))
+    nsq = n0 ** 2 + n1 ** 2 + n2 ** 2
+    k = kf * np.sqrt(nsq)
+    pk = C.linear_pk(k, CO)
+    delta_lin = wk * np.sqrt(pk / (box / np_) ** 3)
+    inner = ((np.abs(n0) < np_ // 2) & (np.abs(n1) < np_ // 2) & (n2 < np_ // 2) & (nsq > 0))
+    inner = np.broadcast_to(inner, wk.shape)
+    np.testing.assert_allclose(div[inner], -delta_lin[inner], rtol=1e-10,
+                               atol=1e-12 * np.abs(delta_lin).max())
+
+
+def test_ic_ensemble_power_matches_linear():
+    # mean P(k) of the linear density over seeds ~ P_lin within cosmic variance
+    np_, box = 16, 64.0
+    radial = pm.ic_radial(np_, box, CO)
+    vc = (box / np_) ** 3
+    acc = 0
+    nseed = 16
+    for seed in range(nseed):
+        wk = M.rfftn(white_noise(np_, seed))
+        n0, n1, n2 = M.wave_integers(np_)
+        nsq = n0 ** 2 + n1 ** 2 + n2 ** 2
+        k = 2 * np.pi / box * np.sqrt(nsq)
+        dl = wk * np.sqrt(C.linear_pk(k, CO) / vc)
+        acc = acc + M.power_spectrum(M.irfftn(dl, np_), box, n_bins=6)[1]
+    k, _, N = M.power_spectrum(white_noise(np_, 0), box, n_bins=6)
+    P = acc / nseed
+    # compare with the shell average of P_lin over the same modes
+    n = np.fft.fftfreq(np_, 1 / np_)
+    nn = np.sqrt(n[:, None, None] ** 2 + n[None, :, None] ** 2 + n[None, None, :] ** 2)
+    b = np.floor(nn + 0.5)
+    plin = C.linear_pk(2 * np.pi / box * nn, CO)
+    for i in range(6):
+        ref = plin[b == i + 1].mean()
+        sig = np.sqrt(2.0 / (N[i] * nseed))
+        assert abs(P[i] / ref - 1) < 5 * sig, (i, P[i] / ref, sig)
+
+
+# ------------------------------------------------------------ forward
+
+def test_plane_wave_tracks_linear_growth():
+    """A small plane wave on a 64^3 lattice and 64^3 mesh grows like D(a)."""
+    np_, mesh, box = 64, 64, 64.0
+    st = pm.Setup(np_, mesh, box, 10, CO)
+    q = pm.lattice(np_, box)
+    kx = 2 * np.pi / box
+    A = 0.01 / kx                      # A k D(1) = 0.01: far from shell crossing
+    s = np.zeros_like(q)
+    s[:, 0] = A * np.sin(kx * q[:, 0])
+    run = pm.forward_from_displacement(s, st)
+    co = C.kdk_coefficients(0.3, st.a_start, st.a_stop, st.n_steps)
+    D = C.growth_D(co.a, 0.3)
+    basis = np.sin(kx * q[:, 0])
+    amp = [np.dot(d[:, 0], basis) / np.dot(basis, basis) for d in run.disp]
+    ratio = np.array(amp) / amp[0]
+    err = np.abs(ratio / (D / D[0]) - 1)
+    assert err.max() < 5e-3, err
+
+
+def test_uniform_lattice_stays_put():
+    st = pm.Setup(8, 16, 16.0, 4, CO)
+    run = pm.forward_from_displacement(np.zeros((512, 3)), st)
+    assert np.max(np.abs(run.disp[-1])) < 1e-12
+    assert np.max(np.abs(run.dens)) < 1e-12
+
+
+def test_total_momentum_conserved():
+    st = tiny(5)
+    run = pm.forward(white_noise(8, 2), st)
+    p0 = run.mom0.sum(axis=0)
+    pN = run.mom.sum(axis=0)
+    assert np.max(np.abs(pN - p0)) < 1e-9 * np.abs(run.mom).sum()
+
+
+def test_fp64_reversibility():
+    st = tiny(6)
+    run = pm.forward(white_noise(8, 3), st)
+    rec, mom0 = pm.reverse_reconstruct(run.disp[-1], run.mom, st)
+    cell = st.box / st.mesh
+    for n in range(st.n_steps + 1):
+        assert np.max(np.abs(rec[n] - run.disp[n])) / cell < 1e-9
+    assert np.max(np.abs(mom0 - run.mom0)) < 1e-9 * np.abs(run.mom0).max()
+
+
+# ------------------------------------------------------------ adjoint
+
+def _loss(noise, st, target, theta=None, wd=None, wp=None):
+    r = pm.forward(noise, st, theta)
+    L = pm.mse_loss(r.dens, target)[0]
+    if wd is not None:
+        L += np.sum(wd * r.disp[-1]) + np.sum(wp * r.mom)
+    return L
+
+
+@pytest.fixture(scope="module")
+def grad_case():
+    st = tiny(4)
+    noise = white_noise(8, 3)
+    target = pm.forward(white_noise(8, 4), st).dens
+    theta = 0.5 * mlp_init(0, zero_last=False)
+    wd, wp = normal((512, 3), 9), normal((512, 3), 10)
+    run = pm.forward(noise, st, theta)
+    _, gd = pm.mse_loss(run.dens, target)
+    g = pm.adjoint(run, noise, g_dens=gd, g_disp=wd, g_mom=wp)
+    return st, noise, target, theta, wd, wp, g
+
+
+def test_gradient_noise_fd(grad_case):
+    st, noise, target, theta, wd, wp, g = grad_case
+    d = normal(noise.shape, 7)
+    h = 1e-6
+    fd = (_loss(noise + h * d, st, target, theta, wd, wp)
+          - _loss(noise - h * d, st, target, theta, wd, wp)) / (2 * h)
+    assert abs(fd / np.sum(g.noise * d) - 1) < 1e-6
+
+
+@pytest.mark.parametrize("name", ["omega_m", "sigma8"])
+def test_gradient_cosmology_fd(grad_case, name):
+    st, noise, target, theta, wd, wp, g = grad_case
+    h = 1e-6
+    c = st.cosmo
+    up = replace(st, cosmo=replace(c, **{name: getattr(c, name) + h}))
+    dn = replace(st, cosmo=replace(c, **{name: getattr(c, name) - h}))
+    fd = (_loss(noise, up, target, theta, wd, wp) - _loss(noise, dn, target, theta, wd, wp)) / (2 * h)
+    assert abs(fd / getattr(g, name) - 1) < 1e-6
+
+
+def test_gradient_filter_weights_fd(grad_case):
+    st, noise, target, theta, wd, wp, g = grad_case
+    d = normal(theta.shape, 5)
+    h = 1e-6
+    fd = (_loss(noise, st, target, theta + h * d, wd, wp)
+          - _loss(noise, st, target, theta - h * d, wd, wp)) / (2 * h)
+    assert abs(fd / np.dot(g.theta, d) - 1) < 1e-6
+
+
+def test_zero_last_layer_is_plain_pm():
+    st = tiny(3)
+    noise = white_noise(8, 6)
+    a = pm.forward(noise, st, None)
+    b = pm.forward(noise, st, mlp_init(0))           # last layer zero: f == 1
+    assert np.array_equal(a.disp[-1], b.disp[-1])
+    assert np.array_equal(a.mom, b.mom)
+
+
+def test_ic_transpose_dot_product():
+    np_, box = 8, 16.0
+    radial = pm.ic_radial(np_, box, CO)
+    w = normal((np_,) * 3, 40)
+    sb = normal((np_ ** 3, 3), 41)
+    lhs = np.sum(pm.zeldovich_displacement(w, box, radial) * sb)
+    rhs = np.sum(w * pm.zeldovich_transpose(sb, box, radial))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
