@@ -1,0 +1,191 @@
+"""Benchmark: forward + reverse-time adjoint particle-steps/s on one MI355X.
+
+One step = one whole pass of the hot path over one batch: Zel'dovich ICs from
+seeded white noise, 63 KDK steps of the PM force (CIC scatter, 3-D real FFT,
+Poisson gradient, 3 inverse FFTs, CIC gather, kick/drift), the MSE loss against
+a second seeded run, and the reverse-time adjoint back to dL/dnoise,
+dL/dOmega_m and dL/dsigma_8.  Throughput = particles * time steps * K / time
+of K such passes, with all inputs resident in HBM.
+
+Prints one JSON line (see the keys below).  `--gpus N` with N > 1 exits: this
+build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+adjoint particle-steps/s at 512³/1024³; learned vs plain speed at 2% P(k)"
+PEAK_HBM_GBS = 8000.0
+FAMILY_KERNELS = {
+    "fft_strided": ["k_fft_strided"], "fft_x": ["k_fft_x_r2c", "k_fft_x_c2r"],
+    "grad_z": ["k_grad_z"], "grad_adj_z": ["k_grad_adj_z"], "scatter": ["k_scatter_tile"],
+    "scatter_vec": ["k_scatter_tile"], "gather": ["k_gather_kick_drift"],
+    "unkick_vjp": ["k_unkick_vjp"], "wgrad": ["k_wgrad"],
+    "bin": ["k_bin_count", "k_scan_local", "k_scan_bsum", "k_scan_add", "k_bin_permute"],
+}
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__)
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", default="pm-512p-1024m-63s")
+    p.add_argument("--checkpoint-every", type=int, default=16)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-pure-variant", action="store_true")
+    p.add_argument("--cpu-only", action="store_true", help="only the oracle CPU baseline")
+    return p.parse_args()
+
+
+def cpu_baseline():
+    """The FP64 oracle, as it stands, on a bounded sample of the workload: 64^3
+    particles on a 128^3 mesh in a 64 Mpc/h box (the headline's cell size and
+    particle spacing), 2 KDK steps, forward + MSE loss + stored-trajectory adjoint."""
+    import numpy as np
+    from oracle import mesh as M
+    from oracle import pm as opm
+    from synthetic import Cosmology, white_noise
+    cores = len(os.sched_getaffinity(0))
+    M.WORKERS = cores
+    st = opm.Setup(64, 128, 64.0, 2, Cosmology())
+    target = opm.forward(white_noise(64, 1), st).dens
+    t0 = time.perf_counter()
+    run = opm.forward(white_noise(64, 0), st)
+    _, gd = opm.mse_loss(run.dens, target)
+    opm.adjoint(run, white_noise(64, 0), g_dens=gd)
+    dt = time.perf_counter() - t0
+    return {"value": 64 ** 3 * 2 / dt, "unit": "particle-steps/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "64^3 particles, 128^3 mesh, box 64 Mpc/h (same cell size and particle "
+                      "spacing as 512^3/1024^3), 2 KDK steps, fwd + MSE loss + adjoint, FP64; "
+                      f"scipy.fft with {cores} workers, CIC single-threaded numpy; {dt:.1f} s"}
+
+
+def traffic_for(family):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    entry = data.get(family)
+    if not entry:
+        return None
+    src = os.path.join(ROOT, "paper_2211_09958_amd", "csrc", entry["source"])
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if sha != entry.get("source_sha256"):
+        return None
+    return entry["hbm_bytes_per_launch"]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    if args.cpu_only:
+        print(json.dumps({"cpu_baseline": cpu_baseline()}))
+        return
+
+    import numpy as np
+    import torch
+
+    from paper_2211_09958_amd import api
+    from synthetic import WORKLOADS, Cosmology, white_noise
+
+    w = WORKLOADS[args.workload]
+    co = Cosmology()
+    P = w.ptcl_grid ** 3
+
+    def make(ck):
+        return api.PMContext(api.config_from_workload(w, checkpoint_every=ck, timing=True), co,
+                             device="cuda:0")
+
+    pm = make(args.checkpoint_every)
+    noise = torch.as_tensor(white_noise(w.ptcl_grid, 0), dtype=torch.float32, device="cuda:0")
+    _, _, target = pm.forward(torch.as_tensor(white_noise(w.ptcl_grid, 1), dtype=torch.float32,
+                                              device="cuda:0"))
+    target = target.clone()
+
+    def step(ctx):
+        disp, mom, dens = ctx.forward(noise)
+        _, g = ctx.loss_mse(dens, target)
+        g_noise, g_cosmo, _ = ctx.adjoint(g_dens=g)
+        return g_cosmo
+
+    for _ in range(args.warmup):
+        step(pm)
+    torch.cuda.synchronize()
+    pm.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g_cosmo = step(pm)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = pm.stats()
+    value = P * w.n_steps * args.steps / dt
+
+    fams = st["kernels"]
+    dom = max(fams, key=lambda k: fams[k]["ms"])
+    f = fams[dom]
+    achieved = f["bytes"] / (f["ms"] * 1e-3) / 1e9 if f["ms"] > 0 else 0.0
+    per_launch = f["bytes"] / max(f["launches"], 1)
+    traffic = traffic_for(dom)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                "kernel": dom, "kernel_symbols": FAMILY_KERNELS.get(dom, []),
+                "avg_launch_ms": f["ms"] / max(f["launches"], 1),
+                "algorithmic_bytes_per_launch": per_launch}
+    total_ms = sum(v["ms"] for v in fams.values())
+    breakdown = {k: {"ms_per_step": v["ms"] / args.steps,
+                     "share": v["ms"] / total_ms if total_ms else 0.0,
+                     "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else 0.0}
+                 for k, v in fams.items() if v["ms"] > 0}
+
+    out = {"metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (seeded white-noise LCDM ICs)",
+           "config": {"workload": w.name if not args.checkpoint_every else
+                      f"{w.name}-ckpt{args.checkpoint_every}",
+                      "ptcl_grid": w.ptcl_grid, "mesh": w.mesh, "box": w.box,
+                      "n_steps": w.n_steps, "checkpoint_every": args.checkpoint_every,
+                      "loss": "MSE of final CIC density vs seed-1 run"},
+           "roofline": roofline,
+           "reconstruction": {"ic_rms_cells": st["ic_rms_cells"], "ic_max_cells": st["ic_max_cells"],
+                              "ckpt_rms_cells": st["ckpt_rms_cells"]},
+           "grad_cosmo": list(g_cosmo), "kernel_breakdown": breakdown}
+
+    if not args.no_pure_variant and args.checkpoint_every:
+        del pm
+        torch.cuda.empty_cache()
+        pure = make(0)
+        step(pure)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step(pure)
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - t0
+        sp = pure.stats()
+        out["pure_reverse"] = {"value": P * w.n_steps / dtp, "ms_per_step": dtp * 1e3,
+                               "ic_rms_cells": sp["ic_rms_cells"],
+                               "ic_max_cells": sp["ic_max_cells"]}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,359 @@
+// Batched 3-D real FFT passes for gfx950 and the fused Fourier-space Poisson
+// gradient (and its transpose).
+//
+// A 3-D transform is three passes over HBM, one per axis:
+//   * last axis (contiguous rows): a real row of n samples is read as n/2
+//     complex pairs, transformed with an n/2-point complex FFT, and split into
+//     the n/2 + 1 half-spectrum values with the standard post-twiddle
+//         X[k] = (Z[k] + Z*[n/2-k]) / 2 - i W^k (Z[k] - Z*[n/2-k]) / 2;
+//   * axes 1 and 0 (strided): a work-group loads an n x W tile (W consecutive
+//     columns, each row segment W*8 bytes) and transforms the W columns
+//     together, exchanging through LDS between Stockham stages.
+// The Poisson multiply F~_j = i k_j f(|k|) delta_k / k^2 is fused into the
+// axis-0 pass: one load of the spectrum, one forward column FFT, then for each
+// j a multiply and inverse column FFT straight to the output buffer, so the
+// spectrum is read once and each gradient component written once.
+#include <type_traits>
+
+#include "fft_engine.h"
+#include "kernels.h"
+
+namespace pmx {
+namespace {
+
+// Lanes-per-transform and values-per-lane choices per transform length.
+template <int H>
+struct Cfg {
+    static constexpr int E = H <= 16 ? H : (H == 256 || H == 1024 ? 16 : 8);
+    static constexpr int T = H / E;
+    // columns per work-group for strided passes: 64 KiB LDS tile at most
+    static constexpr int W = H >= 1024 ? 8 : 16;
+    static constexpr int ROWS = T >= 256 ? 1 : 256 / T;   // rows per work-group, last axis
+};
+
+// ---------------------------------------------------------- last axis
+
+template <int N>
+__global__ void __launch_bounds__(Cfg<N / 2>::T * Cfg<N / 2>::ROWS)
+k_fft_x_r2c(float2* __restrict__ buf, int cs, long nrows, long bufStride,
+            const float2* __restrict__ tw, int ntw) {
+    constexpr int H = N / 2, E = Cfg<H>::E, T = Cfg<H>::T, ROWS = Cfg<H>::ROWS;
+    constexpr int LS = H + 1;
+    __shared__ float2 lds[ROWS * LS];
+    const int r = threadIdx.x / T, j = threadIdx.x % T;
+    const long row = (long)blockIdx.x * ROWS + r;
+    const bool valid = row < nrows;
+    float2* rowp = buf + blockIdx.y * bufStride + (valid ? row : 0) * cs;
+    const int twH = ntw / H, twN = ntw / N;
+    float2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = valid ? rowp[j + e * T] : make_float2(0.f, 0.f);
+    float2* L = lds + r * LS;
+    fft_lds<H, E, -1>(v, L, 1, 0, j, tw, twH);
+    __syncthreads();
+    if (!valid) return;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = j + e * T;
+        float2 zk = L[k], zc = cconj(L[(H - k) & (H - 1)]);
+        float2 A = cadd(zk, zc), B = csub(zk, zc);
+        float2 w = tw[k * twN];
+        float2 iwB = cmul_i<1>(cmul(w, B));
+        float2 X = make_float2(0.5f * (A.x - iwB.x), 0.5f * (A.y - iwB.y));
+        if (k == 0) {
+            X = make_float2(zk.x + zk.y, 0.f);
+            rowp[H] = make_float2(zk.x - zk.y, 0.f);
+        }
+        rowp[k] = X;
+    }
+}
+
+template <int N>
+__global__ void __launch_bounds__(Cfg<N / 2>::T * Cfg<N / 2>::ROWS)
+k_fft_x_c2r(float2* __restrict__ buf, int cs, long nrows, long bufStride,
+            const float2* __restrict__ tw, int ntw) {
+    constexpr int H = N / 2, E = Cfg<H>::E, T = Cfg<H>::T, ROWS = Cfg<H>::ROWS;
+    constexpr int LS = H + 1;
+    __shared__ float2 lds[ROWS * LS];
+    const int r = threadIdx.x / T, j = threadIdx.x % T;
+    const long row = (long)blockIdx.x * ROWS + r;
+    const bool valid = row < nrows;
+    float2* rowp = buf + blockIdx.y * bufStride + (valid ? row : 0) * cs;
+    const int twH = ntw / H, twN = ntw / N;
+    float2* L = lds + r * LS;
+#pragma unroll
+    for (int e = 0; e < E; ++e) L[j + e * T] = valid ? rowp[j + e * T] : make_float2(0.f, 0.f);
+    if (j == 0) L[H] = valid ? rowp[H] : make_float2(0.f, 0.f);
+    __syncthreads();
+    float2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = j + e * T;
+        float2 xk = L[k], xc = cconj(L[H - k]);
+        float2 A = cadd(xk, xc), B = cmulc(csub(xk, xc), tw[k * twN]);
+        v[e] = cadd(A, cmul_i<1>(B));
+    }
+    __syncthreads();
+    fft_lds<H, E, 1>(v, L, 1, 0, j, tw, twH);
+    __syncthreads();
+    if (!valid) return;
+#pragma unroll
+    for (int e = 0; e < E; ++e) rowp[j + e * T] = L[j + e * T];
+}
+
+// ---------------------------------------------------------- strided axes
+
+// Tile t -> (a, cb): column base a*A + cb*W, element p at + p*S.
+template <int H, int DIR>
+__global__ void __launch_bounds__(Cfg<H>::T * Cfg<H>::W)
+k_fft_strided(float2* __restrict__ buf, long S, long A, int ncb, long bufStride,
+              const float2* __restrict__ tw, int ntw) {
+    constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::W;
+    __shared__ float2 lds[H * W];
+    const int c = threadIdx.x % W, j = threadIdx.x / W;
+    const int a = blockIdx.x / ncb, cb = blockIdx.x % ncb;
+    float2* base = buf + blockIdx.y * bufStride + a * A + cb * W + c;
+    float2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = base[(j + e * T) * S];
+    fft_lds<H, E, DIR>(v, lds, W, c, j, tw, ntw / H);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) base[(j + e * T) * S] = lds[(j + e * T) * W + c];
+}
+
+__device__ __forceinline__ int signed_freq(int p, int n) { return p < n / 2 ? p : p - n; }
+
+// Axis-0 pass with the fused gradient multiply (see launch_grad_z).
+template <int H>
+__global__ void __launch_bounds__(Cfg<H>::T * Cfg<H>::W)
+k_grad_z(const float2* __restrict__ src, float2* __restrict__ dst, long dstStride, int cs,
+         int ncb, const float* __restrict__ radial, const float2* __restrict__ tw, int ntw) {
+    constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::W, n = H;
+    __shared__ float2 lds[H * W];
+    const int c = threadIdx.x % W, j = threadIdx.x / W;
+    const int i1 = blockIdx.x / ncb, cb = blockIdx.x % ncb;
+    const int k2 = cb * W + c;
+    const long S = (long)n * cs;
+    const long col = (long)i1 * cs + k2;
+    float2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = src[col + (j + e * T) * S];
+    fft_lds<H, E, -1>(v, lds, W, c, j, tw, ntw / H);
+    __syncthreads();
+    float2 d[E];
+    float rad[E];
+    int n0s[E];
+    const int n1 = signed_freq(i1, n);
+    const bool in_half = k2 <= n / 2;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = j + e * T;
+        d[e] = lds[p * W + c];
+        const int n0 = signed_freq(p, n);
+        n0s[e] = n0;
+        rad[e] = in_half ? radial[n0 * n0 + n1 * n1 + k2 * k2] : 0.f;
+    }
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int nc = comp == 0 ? n0s[e] : (comp == 1 ? n1 : k2);
+            const bool nyq = comp == 0 ? (n0s[e] == -n / 2) : (comp == 1 ? (n1 == -n / 2) : (k2 == n / 2));
+            const float f = nyq ? 0.f : (float)nc * rad[e];
+            v[e] = make_float2(-d[e].y * f, d[e].x * f);
+        }
+        __syncthreads();
+        fft_lds<H, E, 1>(v, lds, W, c, j, tw, ntw / H);
+        __syncthreads();
+        float2* out = dst + comp * dstStride + col;
+#pragma unroll
+        for (int e = 0; e < E; ++e) out[(j + e * T) * S] = lds[(j + e * T) * W + c];
+    }
+}
+
+// Axis-0 pass of the transposed gradient operator (see launch_grad_adj_z).
+template <int H, bool FILT>
+__global__ void __launch_bounds__(Cfg<H>::T * Cfg<H>::W)
+k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
+             const float2* dens, int cs, int ncb, const float* __restrict__ radial,
+             float* __restrict__ fbar, float fscale, const float2* __restrict__ tw, int ntw) {
+    constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::W, n = H;
+    __shared__ float2 lds[H * W];
+    const int c = threadIdx.x % W, j = threadIdx.x / W;
+    const int i1 = blockIdx.x / ncb, cb = blockIdx.x % ncb;
+    const int k2 = cb * W + c;
+    const long S = (long)n * cs;
+    const long col = (long)i1 * cs + k2;
+    const int n1 = signed_freq(i1, n);
+    const bool in_half = k2 <= n / 2;
+    float2 v[E], acc[E], d[E];
+    float fs[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        acc[e] = make_float2(0.f, 0.f);
+        fs[e] = 0.f;
+    }
+    if constexpr (FILT) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = dens[col + (j + e * T) * S];
+        fft_lds<H, E, -1>(v, lds, W, c, j, tw, ntw / H);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) d[e] = lds[(j + e * T) * W + c];
+    }
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+        const float2* in = src + comp * srcStride + col;
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = in[(j + e * T) * S];
+        __syncthreads();
+        fft_lds<H, E, -1>(v, lds, W, c, j, tw, ntw / H);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = j + e * T;
+            const float2 g = lds[p * W + c];
+            const int n0 = signed_freq(p, n);
+            const int nsq = n0 * n0 + n1 * n1 + k2 * k2;
+            const int nc = comp == 0 ? n0 : (comp == 1 ? n1 : k2);
+            const bool nyq = comp == 0 ? (n0 == -n / 2) : (comp == 1 ? (n1 == -n / 2) : (k2 == n / 2));
+            const float f = (nyq || !in_half) ? 0.f : (float)nc * radial[nsq];
+            // conj(i f) g = -i f g
+            acc[e].x += g.y * f;
+            acc[e].y -= g.x * f;
+            if constexpr (FILT) {
+                const float f0 = (nyq || !in_half || nsq == 0) ? 0.f : (float)nc * fscale / (float)nsq;
+                // Re(conj(g) * i f0 d) = f0 * (g.x * (-d.y) + g.y * d.x)
+                fs[e] += f0 * (g.y * d[e].x - g.x * d[e].y);
+            }
+        }
+    }
+    if constexpr (FILT) {
+        if (in_half) {
+            const float mult = (k2 == 0 || k2 == n / 2) ? 1.f : 2.f;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int n0 = signed_freq(j + e * T, n);
+                const int nsq = n0 * n0 + n1 * n1 + k2 * k2;
+                if (nsq > 0) atomicAdd(&fbar[nsq], mult * fs[e]);
+            }
+        }
+    }
+    __syncthreads();
+    fft_lds<H, E, 1>(acc, lds, W, c, j, tw, ntw / H);
+    __syncthreads();
+    float2* out = dst + col;
+#pragma unroll
+    for (int e = 0; e < E; ++e) out[(j + e * T) * S] = lds[(j + e * T) * W + c];
+}
+
+// Calls f(std::integral_constant<int, n>) for the supported power-of-two sizes.
+template <class F>
+void size_switch(int n, F&& f) {
+    switch (n) {
+        case 8: f(std::integral_constant<int, 8>{}); break;
+        case 16: f(std::integral_constant<int, 16>{}); break;
+        case 32: f(std::integral_constant<int, 32>{}); break;
+        case 64: f(std::integral_constant<int, 64>{}); break;
+        case 128: f(std::integral_constant<int, 128>{}); break;
+        case 256: f(std::integral_constant<int, 256>{}); break;
+        case 512: f(std::integral_constant<int, 512>{}); break;
+        case 1024: f(std::integral_constant<int, 1024>{}); break;
+        default: break;
+    }
+}
+
+template <int N>
+void x_r2c(float2* buf, int cs, int nbuf, long bufStride, const float2* tw, int ntw,
+           hipStream_t s) {
+    constexpr int ROWS = Cfg<N / 2>::ROWS, T = Cfg<N / 2>::T;
+    long nrows = (long)N * N;
+    dim3 grid((unsigned)((nrows + ROWS - 1) / ROWS), nbuf);
+    hipLaunchKernelGGL(k_fft_x_r2c<N>, grid, dim3(T * ROWS), 0, s, buf, cs, nrows, bufStride, tw, ntw);
+}
+
+template <int N>
+void x_c2r(float2* buf, int cs, int nbuf, long bufStride, const float2* tw, int ntw,
+           hipStream_t s) {
+    constexpr int ROWS = Cfg<N / 2>::ROWS, T = Cfg<N / 2>::T;
+    long nrows = (long)N * N;
+    dim3 grid((unsigned)((nrows + ROWS - 1) / ROWS), nbuf);
+    hipLaunchKernelGGL(k_fft_x_c2r<N>, grid, dim3(T * ROWS), 0, s, buf, cs, nrows, bufStride, tw, ntw);
+}
+
+template <int N>
+void strided(float2* buf, int cs, int axis, int dir, int nbuf, long bufStride, const float2* tw,
+             int ntw, hipStream_t s) {
+    constexpr int W = Cfg<N>::W, T = Cfg<N>::T;
+    int ncb = cs / W;
+    long S = axis == 1 ? cs : (long)N * cs;
+    long A = axis == 1 ? (long)N * cs : cs;
+    dim3 grid(N * ncb, nbuf);
+    if (dir < 0)
+        hipLaunchKernelGGL((k_fft_strided<N, -1>), grid, dim3(T * W), 0, s, buf, S, A, ncb, bufStride, tw, ntw);
+    else
+        hipLaunchKernelGGL((k_fft_strided<N, 1>), grid, dim3(T * W), 0, s, buf, S, A, ncb, bufStride, tw, ntw);
+}
+
+}  // namespace
+
+void launch_fft_x_r2c(float2* buf, int n, int cs, int nbuf, long bufStride, const float2* tw,
+                      int ntw, hipStream_t s) {
+    size_switch(n, [&](auto nn) { x_r2c<decltype(nn)::value>(buf, cs, nbuf, bufStride, tw, ntw, s); });
+}
+
+void launch_fft_x_c2r(float2* buf, int n, int cs, int nbuf, long bufStride, const float2* tw,
+                      int ntw, hipStream_t s) {
+    size_switch(n, [&](auto nn) { x_c2r<decltype(nn)::value>(buf, cs, nbuf, bufStride, tw, ntw, s); });
+}
+
+void launch_fft_axis(float2* buf, int n, int cs, int axis, int dir, int nbuf, long bufStride,
+                     const float2* tw, int ntw, hipStream_t s) {
+    size_switch(n, [&](auto nn) {
+        strided<decltype(nn)::value>(buf, cs, axis, dir, nbuf, bufStride, tw, ntw, s);
+    });
+}
+
+void launch_grad_z(const float2* src, float2* dst, long dstStride, int n, int cs,
+                   const float* radial, const float2* tw, int ntw, hipStream_t s) {
+    size_switch(n, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        constexpr int W = Cfg<NN>::W, T = Cfg<NN>::T;
+        int ncb = cs / W;
+        hipLaunchKernelGGL(k_grad_z<NN>, dim3(NN * ncb), dim3(T * W), 0, s, src, dst,
+                           dstStride, cs, ncb, radial, tw, ntw);
+    });
+}
+
+void launch_grad_adj_z(const float2* src, long srcStride, float2* dst, const float2* dens,
+                       int n, int cs, const float* radial, float* fbar, float fscale,
+                       const float2* tw, int ntw, hipStream_t s) {
+    size_switch(n, [&](auto nn) {
+        constexpr int NN = decltype(nn)::value;
+        constexpr int W = Cfg<NN>::W, T = Cfg<NN>::T;
+        int ncb = cs / W;
+        if (fbar)
+            hipLaunchKernelGGL((k_grad_adj_z<NN, true>), dim3(NN * ncb), dim3(T * W), 0, s, src,
+                               srcStride, dst, dens, cs, ncb, radial, fbar, fscale, tw, ntw);
+        else
+            hipLaunchKernelGGL((k_grad_adj_z<NN, false>), dim3(NN * ncb), dim3(T * W), 0, s, src,
+                               srcStride, dst, dens, cs, ncb, radial, fbar, fscale, tw, ntw);
+    });
+}
+
+void launch_fft3_r2c(float2* buf, int n, int cs, int nbuf, long bufStride, const float2* tw,
+                     int ntw, hipStream_t s) {
+    launch_fft_x_r2c(buf, n, cs, nbuf, bufStride, tw, ntw, s);
+    launch_fft_axis(buf, n, cs, 1, -1, nbuf, bufStride, tw, ntw, s);
+    launch_fft_axis(buf, n, cs, 0, -1, nbuf, bufStride, tw, ntw, s);
+}
+
+void launch_fft3_c2r(float2* buf, int n, int cs, int nbuf, long bufStride, const float2* tw,
+                     int ntw, hipStream_t s) {
+    launch_fft_axis(buf, n, cs, 0, 1, nbuf, bufStride, tw, ntw, s);
+    launch_fft_axis(buf, n, cs, 1, 1, nbuf, bufStride, tw, ntw, s);
+    launch_fft_x_c2r(buf, n, cs, nbuf, bufStride, tw, ntw, s);
+}
+
+}  // namespace pmx

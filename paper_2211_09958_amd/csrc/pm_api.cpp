@@ -1,0 +1,911 @@
+// libpmx C ABI: context, workspace plan, argument checks and the orchestration
+// of the PM forward run and its reverse-time adjoint (see include/pm.h).
+//
+// Forward (kick-drift-kick with growth-factor coefficients, merged kicks):
+//   ICs -> F(x_0) -> for n = 0..N: gather F(x_n),
+//   p += (kick_b_{n-1} + kick_a_n) F_n   (kick_b_{-1} = kick_a_N = 0),
+//   x += drift_n p (n < N), F(x_{n+1}) ...
+// Adjoint (pmwd paper, Statement of Need: dual equations integrated backward in
+// time with the forward states recovered by reverse time integration; the
+// discrete transpose of the forward steps).  Cotangents xi (positions) and pi
+// (momenta); at each x_m the force's transpose J_F^T[(kick_b_{m-1}+kick_a_m) pi]
+// has three parts: (i) the gather's position derivative, (ii) a CIC scatter of
+// the cotangent through the transposed spectral operator and (iii) the
+// scatter's position derivative.  Walking back from x_{n+1}:
+//   (ii)+(iii) at x_{n+1};  xi complete -> dL/ddrift_n = Sum xi.p_{n+1/2},
+//   pi += drift_n xi, x_n = x_{n+1} - drift_n p_{n+1/2};  recompute F(x_n);
+//   p_{n-1/2} = p_{n+1/2} - (kick_b_{n-1} + kick_a_n) F_n together with (i) at x_n
+//   and Sum pi.F_n (= dL/dkick_a_n = dL/dkick_b_{n-1}).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "host_cosmo.h"
+#include "kernels.h"
+#include "pm.h"
+
+using namespace pmx;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kNParam = 4417;
+constexpr int kExtraSlots = 16 + 2 * PM_MAX_CHECKPOINTS;
+constexpr int kPartials = 4096;
+
+thread_local std::string g_err;
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int check_config(const pm_config* c, std::string* why) {
+    if (!c) { *why = "config is null"; return PM_EINVAL; }
+    if (!is_pow2(c->ptcl_grid) || c->ptcl_grid < 8 || c->ptcl_grid > 1024) {
+        *why = "ptcl_grid must be a power of two in [8, 1024]"; return PM_EINVAL;
+    }
+    if (!is_pow2(c->mesh) || c->mesh < 8 || c->mesh > 1024) {
+        *why = "mesh must be a power of two in [8, 1024]"; return PM_EINVAL;
+    }
+    if (c->mesh % c->ptcl_grid != 0) { *why = "mesh must be a multiple of ptcl_grid"; return PM_EINVAL; }
+    if (!(c->box > 0.0) || !std::isfinite(c->box)) { *why = "box must be positive"; return PM_EINVAL; }
+    if (!(c->a_start > 0.0 && c->a_stop > c->a_start) || !std::isfinite(c->a_stop)) {
+        *why = "need 0 < a_start < a_stop"; return PM_EINVAL;
+    }
+    if (c->n_steps < 1 || c->n_steps > 100000) { *why = "n_steps must be >= 1"; return PM_EINVAL; }
+    if (c->checkpoint_every < 0) { *why = "checkpoint_every must be >= 0"; return PM_EINVAL; }
+    if (c->checkpoint_every > 0 && (c->n_steps - 1) / c->checkpoint_every > PM_MAX_CHECKPOINTS) {
+        *why = "too many checkpoints"; return PM_EINVAL;
+    }
+    if (c->filter != 0 && c->filter != 1) { *why = "filter must be 0 or 1"; return PM_EINVAL; }
+    if ((c->flags & ~(uint64_t)PM_F_TIMING) != 0) { *why = "unknown flags"; return PM_EINVAL; }
+    return PM_OK;
+}
+
+int check_cosmo(const pm_cosmology* c, std::string* why) {
+    if (!c) { *why = "cosmology is null"; return PM_EINVAL; }
+    if (!(c->omega_m > 0.0 && c->omega_m <= 1.0)) { *why = "omega_m must be in (0, 1]"; return PM_EINVAL; }
+    if (!(c->omega_b >= 0.0 && c->omega_b < c->omega_m)) { *why = "need 0 <= omega_b < omega_m"; return PM_EINVAL; }
+    if (!(c->h > 0.0) || !(c->sigma8 > 0.0) || !std::isfinite(c->n_s)) {
+        *why = "h and sigma8 must be positive, n_s finite"; return PM_EINVAL;
+    }
+    return PM_OK;
+}
+
+Cosmo to_cosmo(const pm_cosmology* c) {
+    return Cosmo{c->omega_m, c->omega_b, c->h, c->sigma8, c->n_s, c->T_cmb > 0 ? c->T_cmb : 2.7255};
+}
+
+int n_checkpoints(const pm_config& c) {
+    return c.checkpoint_every > 0 ? (c.n_steps - 1) / c.checkpoint_every : 0;
+}
+
+// Workspace plan: byte offsets of every buffer, 256-byte aligned.
+struct Plan {
+    size_t total = 0;
+    size_t cplx, disp, mom, xi, pi, fin_disp, fin_mom, s_ic, tmpv, noise, ckpt;
+    size_t counts, offsets, keys, ranks, perm, scan_tmp;
+    size_t radial_f, radial_ic, radial_ic_dom, tw, partials, sums, maxbits, pkbins;
+    size_t theta, gtheta, fbar, mlp_scratch;
+    long cplx_elems, P, nkeys, ntab_f, ntab_p;
+    int cs, cs_p, tile, nt, nckpt;
+
+    size_t take(size_t bytes) {
+        size_t off = total;
+        total += (bytes + 255) / 256 * 256;
+        return off;
+    }
+    explicit Plan(const pm_config& c) {
+        const int ng = c.mesh, np = c.ptcl_grid;
+        cs = complex_row_stride(ng);
+        cs_p = complex_row_stride(np);
+        cplx_elems = (long)ng * ng * cs;
+        P = (long)np * np * np;
+        tile = choose_tile(ng);
+        nt = ng / tile;
+        nkeys = (long)nt * nt * nt * 8;
+        ntab_f = 3L * (ng / 2) * (ng / 2) + 1;
+        ntab_p = 3L * (np / 2) * (np / 2) + 1;
+        nckpt = n_checkpoints(c);
+        const size_t vec = (size_t)P * 3 * sizeof(float);
+        cplx = take(4 * (size_t)cplx_elems * sizeof(float2));
+        disp = take(vec);
+        mom = take(vec);
+        xi = take(vec);
+        pi = take(vec);
+        fin_disp = take(vec);
+        fin_mom = take(vec);
+        s_ic = take(vec);
+        tmpv = take(vec);
+        noise = take((size_t)P * sizeof(float));
+        ckpt = take((size_t)nckpt * 2 * vec);
+        counts = take((nkeys + 1) * sizeof(uint32_t));
+        offsets = take((nkeys + 1) * sizeof(uint32_t));
+        keys = take((size_t)P * sizeof(uint32_t));
+        ranks = take((size_t)P * sizeof(uint32_t));
+        perm = take((size_t)P * sizeof(uint32_t));
+        scan_tmp = take(scan_tmp_elems(nkeys) * sizeof(uint32_t));
+        radial_f = take(ntab_f * sizeof(float));
+        radial_ic = take(ntab_p * sizeof(float));
+        radial_ic_dom = take(ntab_p * sizeof(float));
+        tw = take((size_t)ng * sizeof(float2));
+        partials = take(kPartials * sizeof(double));
+        sums = take((2 * (size_t)c.n_steps + 2 + kExtraSlots) * sizeof(double));
+        maxbits = take(kExtraSlots * sizeof(unsigned));
+        pkbins = take(3 * (size_t)ng * sizeof(double));
+        theta = take(kNParam * sizeof(float));
+        gtheta = take(kNParam * sizeof(float));
+        fbar = take(c.filter ? ntab_f * sizeof(float) : 0);
+        mlp_scratch = take(c.filter ? mlp_backward_scratch(ng) * sizeof(float) : 0);
+    }
+};
+
+}  // namespace
+
+struct pm_ctx {
+    pm_config cfg;
+    pm_cosmology cosmo;
+    hipStream_t stream;
+    char* ws;
+    size_t ws_bytes;
+    Plan plan;
+    Lattice lat;
+    Bins bins;
+    int np, ng, cs, cs_p;
+    long P;
+    float2* C[4];
+    float *disp, *mom, *xi, *pi, *fin_disp, *fin_mom, *s_ic, *tmpv, *noise, *ckpt;
+    float *radial_f, *radial_ic, *radial_ic_dom, *theta, *gtheta, *fbar, *mlp_scratch;
+    float2* tw;
+    double *partials, *sums, *pkbins;
+    unsigned* maxbits;
+    Schedule sched, dsched;
+    bool have_forward = false;
+    bool have_filter = false;
+    std::string err;
+    pm_stats stats;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // PM_F_TIMING: event pairs around launches, flushed into the stats
+    static constexpr int kPool = 2048;
+    bool timing = false;
+    std::vector<hipEvent_t> pool;
+    struct Pending { int cls; double bytes; int slot; };
+    std::vector<Pending> pending;
+
+    pm_ctx(const pm_config& c) : cfg(c), plan(c) {}
+    void flush_timing() {
+        if (pending.empty()) return;
+        (void)hipEventSynchronize(pool[2 * pending.back().slot + 1]);
+        for (const Pending& q : pending) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, pool[2 * q.slot], pool[2 * q.slot + 1]) == hipSuccess) {
+                stats.kernel_ms[q.cls] += ms;
+                stats.kernel_launches[q.cls] += 1;
+                stats.kernel_bytes[q.cls] += q.bytes;
+            }
+        }
+        pending.clear();
+    }
+    int acquire_slot() {
+        if ((int)pending.size() == kPool) flush_timing();
+        return (int)pending.size();
+    }
+    template <class Tp>
+    Tp* at(size_t off) { return reinterpret_cast<Tp*>(ws + off); }
+    int fail(int code, const std::string& msg) {
+        err = msg;
+        return code;
+    }
+    int hip_check(const char* where) {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(PM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+        return PM_OK;
+    }
+    float* creal(int k) { return reinterpret_cast<float*>(C[k]); }
+    long creal_stride() const { return 2 * plan.cplx_elems; }
+    float mass() const { return (float)(lat.ratio * lat.ratio * lat.ratio); }
+};
+
+namespace {
+
+// Times the launches enqueued during its lifetime (PM_F_TIMING), attributing
+// `bytes` of algorithmic HBM traffic to kernel family `cls`.
+struct KTimer {
+    pm_ctx* c;
+    int cls;
+    double bytes;
+    int slot = -1;
+    KTimer(pm_ctx* ctx, int k, double b) : c(ctx), cls(k), bytes(b) {
+        if (c->timing) {
+            slot = c->acquire_slot();
+            (void)hipEventRecord(c->pool[2 * slot], c->stream);
+        }
+    }
+    ~KTimer() {
+        if (slot >= 0) {
+            (void)hipEventRecord(c->pool[2 * slot + 1], c->stream);
+            c->pending.push_back({cls, bytes, slot});
+        }
+    }
+};
+
+// Algorithmic bytes: real mesh, half spectrum and one particle of FP32.
+double mesh_r(int n) { return 4.0 * n * (double)n * n; }
+double mesh_c(int n) { return 8.0 * n * (double)n * (n / 2 + 1); }
+
+#define PM_TRY(expr)                 \
+    do {                             \
+        int _rc = (expr);            \
+        if (_rc != PM_OK) return _rc; \
+    } while (0)
+
+// Upload the cosmology-dependent tables (schedule on host; P(k) tables to the GPU).
+int upload_tables(pm_ctx* ctx) {
+    const pm_config& c = ctx->cfg;
+    Cosmo co = to_cosmo(&ctx->cosmo);
+    ctx->sched = schedule(co.omega_m, c.a_start, c.a_stop, c.n_steps);
+    ctx->dsched = schedule_domega(co.omega_m, c.a_start, c.a_stop, c.n_steps);
+    const int np = ctx->np, ng = ctx->ng;
+    const long ntp = ctx->plan.ntab_p, ntf = ctx->plan.ntab_f;
+    std::vector<double> pk = pk_table(co, c.box, (int)(ntp - 1));
+    std::vector<double> dpk = pk_table_domega(co, c.box, (int)(ntp - 1));
+    const double vcell = std::pow(c.box / np, 3.0);
+    const double norm_p = c.box / (2.0 * kPi) / ((double)np * np * np);
+    std::vector<float> ric(ntp), ricd(ntp), rf(ntf);
+    for (long n2 = 0; n2 < ntp; ++n2) {
+        if (n2 == 0 || pk[n2] <= 0.0) {
+            ric[n2] = 0.f;
+            ricd[n2] = 0.f;
+            continue;
+        }
+        const double sq = std::sqrt(pk[n2] / vcell);
+        ric[n2] = (float)(sq * norm_p / n2);
+        // d sqrt(P/V)/dOm = dP/dOm / (2 sqrt(P V))
+        ricd[n2] = (float)(dpk[n2] / (2.0 * std::sqrt(pk[n2] * vcell)) * norm_p / n2);
+    }
+    const double norm_f = c.box / (2.0 * kPi) / ((double)ng * ng * ng);
+    for (long n2 = 0; n2 < ntf; ++n2) rf[n2] = n2 == 0 ? 0.f : (float)(norm_f / n2);
+    std::vector<float2> tw(ng);
+    for (int m = 0; m < ng; ++m) {
+        const double ang = -2.0 * kPi * m / ng;
+        tw[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    hipStream_t s = ctx->stream;
+    if (hipMemcpyAsync(ctx->radial_ic, ric.data(), ntp * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(ctx->radial_ic_dom, ricd.data(), ntp * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(ctx->radial_f, rf.data(), ntf * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(ctx->tw, tw.data(), ng * sizeof(float2), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return ctx->fail(PM_EHIP, "uploading tables failed");
+    return PM_OK;
+}
+
+// radial table of the force at scale factor a (plain: precomputed; learned: MLP).
+const float* force_radial(pm_ctx* ctx, double a) {
+    if (ctx->cfg.filter) {
+        const float fscale = (float)(ctx->cfg.box / (2.0 * kPi) / std::pow((double)ctx->ng, 3.0));
+        launch_mlp_table(ctx->theta, ctx->ng, (float)ctx->cfg.box, (float)a, fscale,
+                         ctx->radial_f, nullptr, ctx->stream);
+    }
+    return ctx->radial_f;
+}
+
+// PM force meshes of particles at q + disp: bins, delta -> C0 (x,y-transformed
+// spectrum left in C0), F~_j real meshes in C1..C3.
+void compute_force(pm_ctx* ctx, const float* disp, double a) {
+    hipStream_t s = ctx->stream;
+    const int ng = ctx->ng, cs = ctx->cs;
+    const long cst = ctx->plan.cplx_elems;
+    const double r = mesh_r(ng), c = mesh_c(ng), P = (double)ctx->P;
+    { KTimer t(ctx, PM_K_BIN, 32 * P); launch_bin(disp, ctx->lat, ctx->bins, s); }
+    { KTimer t(ctx, PM_K_SCATTER, 16 * P + r);
+      launch_scatter_density(disp, ctx->lat, ctx->bins, ctx->creal(0), s); }
+    { KTimer t(ctx, PM_K_FFT_X, r + c); launch_fft_x_r2c(ctx->C[0], ng, cs, 1, cst, ctx->tw, ng, s); }
+    { KTimer t(ctx, PM_K_FFT_STRIDED, 2 * c);
+      launch_fft_axis(ctx->C[0], ng, cs, 1, -1, 1, cst, ctx->tw, ng, s); }
+    const float* radial;
+    { KTimer t(ctx, PM_K_MLP, 0); radial = force_radial(ctx, a); }
+    { KTimer t(ctx, PM_K_GRAD_Z, 4 * c);
+      launch_grad_z(ctx->C[0], ctx->C[1], cst, ng, cs, radial, ctx->tw, ng, s); }
+    { KTimer t(ctx, PM_K_FFT_STRIDED, 6 * c);
+      launch_fft_axis(ctx->C[1], ng, cs, 1, 1, 3, cst, ctx->tw, ng, s); }
+    { KTimer t(ctx, PM_K_FFT_X, 3 * (r + c)); launch_fft_x_c2r(ctx->C[1], ng, cs, 3, cst, ctx->tw, ng, s); }
+}
+
+// delta_bar (real, in C0) = transposed spectral operator applied to the CIC
+// scatter of coeff * v at the current bins; filter cotangent into gtheta.
+void vjp_mesh(pm_ctx* ctx, const float* disp, const float* v, float coeff, double a) {
+    hipStream_t s = ctx->stream;
+    const int ng = ctx->ng, cs = ctx->cs;
+    const long cst = ctx->plan.cplx_elems;
+    const double r = mesh_r(ng), c = mesh_c(ng), P = (double)ctx->P;
+    { KTimer t(ctx, PM_K_SCATTER_VEC, 28 * P + 3 * r);
+      launch_scatter_vec(disp, v, coeff, ctx->lat, ctx->bins, ctx->creal(1), ctx->creal_stride(), s); }
+    { KTimer t(ctx, PM_K_FFT_X, 3 * (r + c)); launch_fft_x_r2c(ctx->C[1], ng, cs, 3, cst, ctx->tw, ng, s); }
+    { KTimer t(ctx, PM_K_FFT_STRIDED, 6 * c);
+      launch_fft_axis(ctx->C[1], ng, cs, 1, -1, 3, cst, ctx->tw, ng, s); }
+    float* fbar = nullptr;
+    const float fscale = (float)(ctx->cfg.box / (2.0 * kPi) / std::pow((double)ng, 3.0));
+    if (ctx->cfg.filter) {
+        fbar = ctx->fbar;
+        launch_zero(fbar, ctx->plan.ntab_f * sizeof(float), s);
+    }
+    { KTimer t(ctx, PM_K_GRAD_ADJ_Z, (fbar ? 5 : 4) * c);
+      launch_grad_adj_z(ctx->C[1], cst, ctx->C[0], ctx->C[0], ng, cs, ctx->radial_f, fbar, fscale,
+                        ctx->tw, ng, s); }
+    if (ctx->cfg.filter) {
+        KTimer t(ctx, PM_K_MLP, 0);
+        launch_mlp_backward(ctx->theta, ng, (float)ctx->cfg.box, (float)a, fbar, ctx->gtheta,
+                            ctx->mlp_scratch, mlp_backward_scratch(ng), s);
+    }
+    { KTimer t(ctx, PM_K_FFT_STRIDED, 2 * c);
+      launch_fft_axis(ctx->C[0], ng, cs, 1, 1, 1, cst, ctx->tw, ng, s); }
+    { KTimer t(ctx, PM_K_FFT_X, r + c); launch_fft_x_c2r(ctx->C[0], ng, cs, 1, cst, ctx->tw, ng, s); }
+}
+
+// Zel'dovich displacement (a = 1) of the stored noise with the radial table:
+// writes s_out [P][3] (and disp = D0 s, mom = G0 s when given).
+void ic_synthesis(pm_ctx* ctx, const float* radial, float* s_out, float* disp, float* mom) {
+    hipStream_t s = ctx->stream;
+    const int np = ctx->np, cs = ctx->cs_p, ng = ctx->ng;
+    const long cst = ctx->plan.cplx_elems;
+    const long rp = 2L * cs;
+    launch_to_pitched(ctx->noise, ctx->creal(0), np, rp, 1.f, s);
+    launch_fft_x_r2c(ctx->C[0], np, cs, 1, cst, ctx->tw, ng, s);
+    launch_fft_axis(ctx->C[0], np, cs, 1, -1, 1, cst, ctx->tw, ng, s);
+    launch_grad_z(ctx->C[0], ctx->C[1], cst, np, cs, radial, ctx->tw, ng, s);
+    launch_fft_axis(ctx->C[1], np, cs, 1, 1, 3, cst, ctx->tw, ng, s);
+    launch_fft_x_c2r(ctx->C[1], np, cs, 3, cst, ctx->tw, ng, s);
+    launch_ic_state(ctx->creal(1), ctx->creal_stride(), np, rp, (float)ctx->sched.D0,
+                    (float)ctx->sched.G0, disp, mom, s_out, s);
+}
+
+// dL/dnoise = transpose of the Zel'dovich synthesis applied to s_bar [P][3].
+void ic_transpose(pm_ctx* ctx, const float* s_bar, float* g_noise) {
+    hipStream_t s = ctx->stream;
+    const int np = ctx->np, cs = ctx->cs_p, ng = ctx->ng;
+    const long cst = ctx->plan.cplx_elems;
+    const long rp = 2L * cs;
+    launch_deinterleave(s_bar, ctx->creal(1), ctx->creal_stride(), np, rp, s);
+    launch_fft_x_r2c(ctx->C[1], np, cs, 3, cst, ctx->tw, ng, s);
+    launch_fft_axis(ctx->C[1], np, cs, 1, -1, 3, cst, ctx->tw, ng, s);
+    launch_grad_adj_z(ctx->C[1], cst, ctx->C[0], ctx->C[0], np, cs, ctx->radial_ic, nullptr, 0.f,
+                      ctx->tw, ng, s);
+    launch_fft_axis(ctx->C[0], np, cs, 1, 1, 1, cst, ctx->tw, ng, s);
+    launch_fft_x_c2r(ctx->C[0], np, cs, 1, cst, ctx->tw, ng, s);
+    launch_from_pitched(ctx->creal(0), g_noise, np, rp, s);
+}
+
+int copy_d2d(pm_ctx* ctx, void* dst, const void* src, size_t bytes) {
+    if (hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
+        return ctx->fail(PM_EHIP, "device copy failed");
+    return PM_OK;
+}
+
+int ctx_check(pm_ctx* ctx) {
+    if (!ctx) {
+        g_err = "context is null";
+        return PM_EINVAL;
+    }
+    return PM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pm_workspace_bytes(const pm_config* cfg, int* status) {
+    std::string why;
+    int rc = check_config(cfg, &why);
+    if (status) *status = rc;
+    if (rc != PM_OK) {
+        g_err = why;
+        return 0;
+    }
+    return Plan(*cfg).total;
+}
+
+int pm_host_tables(const pm_config* cfg, const pm_cosmology* cosmo, double* coeffs,
+                   double* dcoeffs, double* growth_out, double* pk_out) {
+    std::string why;
+    int rc = check_config(cfg, &why);
+    if (rc == PM_OK) rc = check_cosmo(cosmo, &why);
+    if (rc != PM_OK) {
+        g_err = why;
+        return rc;
+    }
+    Cosmo co = to_cosmo(cosmo);
+    const int N = cfg->n_steps;
+    auto fill = [N](const Schedule& s, double* out) {
+        for (int n = 0; n < N; ++n) {
+            out[n] = s.kick_a[n];
+            out[N + n] = s.drift[n];
+            out[2 * N + n] = s.kick_b[n];
+        }
+        out[3 * N] = s.D0;
+        out[3 * N + 1] = s.G0;
+    };
+    Schedule s = schedule(co.omega_m, cfg->a_start, cfg->a_stop, N);
+    if (coeffs) fill(s, coeffs);
+    if (dcoeffs) fill(schedule_domega(co.omega_m, cfg->a_start, cfg->a_stop, N), dcoeffs);
+    if (growth_out)
+        for (int n = 0; n <= N; ++n) {
+            growth_out[n] = s.D[n];
+            growth_out[N + 1 + n] = s.dD[n];
+            growth_out[2 * (N + 1) + n] = s.G[n];
+        }
+    if (pk_out) {
+        const int n2max = 3 * (cfg->ptcl_grid / 2) * (cfg->ptcl_grid / 2);
+        std::vector<double> t = pk_table(co, cfg->box, n2max);
+        std::memcpy(pk_out, t.data(), t.size() * sizeof(double));
+    }
+    return PM_OK;
+}
+
+int pm_init(const pm_config* cfg, const pm_cosmology* cosmo, void* workspace, size_t ws_bytes,
+            void* hip_stream, pm_ctx** out) {
+    std::string why;
+    int rc = check_config(cfg, &why);
+    if (rc == PM_OK) rc = check_cosmo(cosmo, &why);
+    if (rc == PM_OK && (!workspace || !out)) {
+        why = "workspace and out must be non-null";
+        rc = PM_EINVAL;
+    }
+    if (rc == PM_OK && (reinterpret_cast<uintptr_t>(workspace) & 255u)) {
+        why = "workspace must be 256-byte aligned";
+        rc = PM_EINVAL;
+    }
+    if (rc == PM_OK && ws_bytes < Plan(*cfg).total) {
+        why = "workspace too small";
+        rc = PM_ENOMEM;
+    }
+    if (rc != PM_OK) {
+        g_err = why;
+        return rc;
+    }
+    pm_ctx* ctx = new pm_ctx(*cfg);
+    ctx->cosmo = *cosmo;
+    ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    ctx->ws = static_cast<char*>(workspace);
+    ctx->ws_bytes = ws_bytes;
+    const Plan& p = ctx->plan;
+    ctx->np = cfg->ptcl_grid;
+    ctx->ng = cfg->mesh;
+    ctx->cs = p.cs;
+    ctx->cs_p = p.cs_p;
+    ctx->P = p.P;
+    for (int k = 0; k < 4; ++k) ctx->C[k] = ctx->at<float2>(p.cplx) + k * p.cplx_elems;
+    ctx->disp = ctx->at<float>(p.disp);
+    ctx->mom = ctx->at<float>(p.mom);
+    ctx->xi = ctx->at<float>(p.xi);
+    ctx->pi = ctx->at<float>(p.pi);
+    ctx->fin_disp = ctx->at<float>(p.fin_disp);
+    ctx->fin_mom = ctx->at<float>(p.fin_mom);
+    ctx->s_ic = ctx->at<float>(p.s_ic);
+    ctx->tmpv = ctx->at<float>(p.tmpv);
+    ctx->noise = ctx->at<float>(p.noise);
+    ctx->ckpt = ctx->at<float>(p.ckpt);
+    ctx->radial_f = ctx->at<float>(p.radial_f);
+    ctx->radial_ic = ctx->at<float>(p.radial_ic);
+    ctx->radial_ic_dom = ctx->at<float>(p.radial_ic_dom);
+    ctx->tw = ctx->at<float2>(p.tw);
+    ctx->partials = ctx->at<double>(p.partials);
+    ctx->sums = ctx->at<double>(p.sums);
+    ctx->maxbits = ctx->at<unsigned>(p.maxbits);
+    ctx->pkbins = ctx->at<double>(p.pkbins);
+    ctx->theta = ctx->at<float>(p.theta);
+    ctx->gtheta = ctx->at<float>(p.gtheta);
+    ctx->fbar = ctx->at<float>(p.fbar);
+    ctx->mlp_scratch = ctx->at<float>(p.mlp_scratch);
+    ctx->lat = Lattice{ctx->np, ctx->ng, ctx->ng / ctx->np, (float)(ctx->ng / cfg->box), 2L * p.cs};
+    ctx->bins.tile = p.tile;
+    ctx->bins.nt = p.nt;
+    ctx->bins.counts = ctx->at<uint32_t>(p.counts);
+    ctx->bins.offsets = ctx->at<uint32_t>(p.offsets);
+    ctx->bins.keys = ctx->at<uint32_t>(p.keys);
+    ctx->bins.ranks = ctx->at<uint32_t>(p.ranks);
+    ctx->bins.perm = ctx->at<uint32_t>(p.perm);
+    ctx->bins.scan_tmp = ctx->at<uint32_t>(p.scan_tmp);
+    std::memset(&ctx->stats, 0, sizeof(ctx->stats));
+    ctx->stats.workspace_bytes = p.total;
+    for (int k = 0; k < 4; ++k)
+        if (hipEventCreate(&ctx->ev[k]) != hipSuccess) {
+            g_err = "hipEventCreate failed";
+            delete ctx;
+            return PM_EHIP;
+        }
+    if (cfg->flags & PM_F_TIMING) {
+        ctx->timing = true;
+        ctx->pool.assign(2 * pm_ctx::kPool, nullptr);
+        for (hipEvent_t& e : ctx->pool)
+            if (hipEventCreate(&e) != hipSuccess) {
+                g_err = "hipEventCreate failed";
+                pm_destroy(ctx);
+                return PM_EHIP;
+            }
+    }
+    rc = upload_tables(ctx);
+    if (rc == PM_OK) {
+        launch_zero(ctx->theta, kNParam * sizeof(float), ctx->stream);
+        rc = ctx->hip_check("pm_init");
+    }
+    if (rc != PM_OK) {
+        g_err = ctx->err;
+        pm_destroy(ctx);
+        return rc;
+    }
+    *out = ctx;
+    return PM_OK;
+}
+
+int pm_set_cosmology(pm_ctx* ctx, const pm_cosmology* cosmo) {
+    PM_TRY(ctx_check(ctx));
+    std::string why;
+    if (check_cosmo(cosmo, &why) != PM_OK) return ctx->fail(PM_EINVAL, why);
+    ctx->cosmo = *cosmo;
+    ctx->have_forward = false;
+    return upload_tables(ctx);
+}
+
+int pm_set_filter(pm_ctx* ctx, const float* weights_dev) {
+    PM_TRY(ctx_check(ctx));
+    if (!ctx->cfg.filter) return ctx->fail(PM_ESTATE, "context was created with filter = 0");
+    if (!weights_dev) return ctx->fail(PM_EINVAL, "weights are null");
+    PM_TRY(copy_d2d(ctx, ctx->theta, weights_dev, kNParam * sizeof(float)));
+    ctx->have_forward = false;
+    ctx->have_filter = true;
+    return ctx->hip_check("pm_set_filter");
+}
+
+int pm_forward(pm_ctx* ctx, const float* noise, float* disp_out, float* mom_out, float* dens) {
+    PM_TRY(ctx_check(ctx));
+    if (!noise || !disp_out || !mom_out) return ctx->fail(PM_EINVAL, "noise, disp and mom are required");
+    if (ctx->cfg.filter && !ctx->have_filter) return ctx->fail(PM_ESTATE, "pm_set_filter not called");
+    hipStream_t s = ctx->stream;
+    const pm_config& c = ctx->cfg;
+    const Schedule& sc = ctx->sched;
+    const int N = c.n_steps;
+    const size_t vec = (size_t)ctx->P * 3 * sizeof(float);
+    hipEventRecord(ctx->ev[0], s);
+    PM_TRY(copy_d2d(ctx, ctx->noise, noise, (size_t)ctx->P * sizeof(float)));
+    ic_synthesis(ctx, ctx->radial_ic, ctx->s_ic, ctx->disp, ctx->mom);
+    for (int n = 0; n <= N; ++n) {
+        compute_force(ctx, ctx->disp, sc.a[n]);
+        const double kick = (n > 0 ? sc.kick_b[n - 1] : 0.0) + (n < N ? sc.kick_a[n] : 0.0);
+        float *ckd = nullptr, *ckm = nullptr;
+        if (c.checkpoint_every > 0 && n > 0 && n < N && n % c.checkpoint_every == 0) {
+            const int slot = n / c.checkpoint_every - 1;
+            ckd = ctx->ckpt + (size_t)slot * 6 * ctx->P;
+            ckm = ckd + 3 * ctx->P;
+        }
+        KTimer t(ctx, PM_K_GATHER, (ckd ? 72.0 : 48.0) * ctx->P + 3 * mesh_r(ctx->ng));
+        launch_gather_kick_drift(ctx->disp, ctx->mom, ctx->creal(1), ctx->creal_stride(), ctx->lat,
+                                 (float)kick, n < N ? (float)sc.drift[n] : 0.f, n < N, ckd, ckm, s);
+    }
+    PM_TRY(copy_d2d(ctx, ctx->fin_disp, ctx->disp, vec));
+    PM_TRY(copy_d2d(ctx, ctx->fin_mom, ctx->mom, vec));
+    PM_TRY(copy_d2d(ctx, disp_out, ctx->disp, vec));
+    PM_TRY(copy_d2d(ctx, mom_out, ctx->mom, vec));
+    if (dens) {
+        launch_bin(ctx->disp, ctx->lat, ctx->bins, s);
+        launch_scatter_density(ctx->disp, ctx->lat, ctx->bins, ctx->creal(0), s);
+        launch_from_pitched(ctx->creal(0), dens, ctx->ng, ctx->lat.rp, s);
+    }
+    hipEventRecord(ctx->ev[1], s);
+    PM_TRY(ctx->hip_check("pm_forward"));
+    ctx->have_forward = true;
+    return PM_OK;
+}
+
+int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const float* g_mom,
+               float* g_noise, double* g_cosmo, float* g_filter) {
+    PM_TRY(ctx_check(ctx));
+    if (!g_noise) return ctx->fail(PM_EINVAL, "g_noise is required");
+    if (g_filter && !ctx->cfg.filter) return ctx->fail(PM_EINVAL, "g_filter needs filter = 1");
+    if (!ctx->have_forward) return ctx->fail(PM_ESTATE, "pm_adjoint needs a preceding pm_forward");
+    hipStream_t s = ctx->stream;
+    const pm_config& c = ctx->cfg;
+    const Schedule& sc = ctx->sched;
+    const int N = c.n_steps;
+    const long P = ctx->P;
+    const size_t vec = (size_t)P * 3 * sizeof(float);
+    const int nb = particle_blocks(P);
+    const int slotS = 0, slotD = N + 1, slotX = 2 * N + 1;   // S_m, D_n, extras
+    const int xD0 = slotX, xG0 = slotX + 1, xSig = slotX + 2, xOm = slotX + 3,
+              xIc = slotX + 4, xIcMom = slotX + 5, xIcMomRef = slotX + 6, xCk = slotX + 8;
+    const float mass = ctx->mass();
+    hipEventRecord(ctx->ev[2], s);
+    PM_TRY(copy_d2d(ctx, ctx->disp, ctx->fin_disp, vec));
+    PM_TRY(copy_d2d(ctx, ctx->mom, ctx->fin_mom, vec));
+    launch_zero(ctx->sums, (2 * (size_t)N + 2 + kExtraSlots) * sizeof(double), s);
+    launch_zero(ctx->maxbits, kExtraSlots * sizeof(unsigned), s);
+    if (c.filter) launch_zero(ctx->gtheta, kNParam * sizeof(float), s);
+    if (g_mom) PM_TRY(copy_d2d(ctx, ctx->pi, g_mom, vec));
+    else launch_zero(ctx->pi, vec, s);
+
+    // seed at x_N: xi = dL/dx_N (+ m grad w . dL/ddelta)
+    compute_force(ctx, ctx->disp, sc.a[N]);
+    if (g_dens)
+        launch_wgrad(g_dens, ctx->ng, mass, ctx->disp, ctx->mom, ctx->xi, ctx->pi, g_disp, ctx->lat,
+                     0.f, 0, nullptr, nb, s);
+    else if (g_disp)
+        PM_TRY(copy_d2d(ctx, ctx->xi, g_disp, vec));
+    else
+        launch_zero(ctx->xi, vec, s);
+    const double bytes_unkick = 72.0 * P + 3 * mesh_r(ctx->ng);
+    const double bytes_wgrad = 84.0 * P + mesh_r(ctx->ng);
+    {
+        KTimer t(ctx, PM_K_UNKICK_VJP, bytes_unkick);
+        launch_unkick_vjp(ctx->disp, ctx->mom, ctx->creal(1), ctx->creal_stride(), ctx->lat,
+                          (float)sc.kick_b[N - 1], ctx->pi, ctx->xi, ctx->partials, nb, 1, s);
+    }
+    launch_reduce(ctx->partials, nb, ctx->sums, slotS + N, s);
+
+    int nck = 0;
+    for (int n = N - 1; n >= 0; --n) {
+        // (ii) + (iii) at x_{n+1}
+        const double c1 = sc.kick_b[n] + (n + 1 < N ? sc.kick_a[n + 1] : 0.0);
+        vjp_mesh(ctx, ctx->disp, ctx->pi, (float)c1, sc.a[n + 1]);
+        {
+            KTimer t(ctx, PM_K_WGRAD, bytes_wgrad);
+            launch_wgrad(ctx->creal(0), ctx->lat.rp, mass, ctx->disp, ctx->mom, ctx->xi, ctx->pi,
+                         nullptr, ctx->lat, (float)sc.drift[n], 1, ctx->partials, nb, s);
+        }
+        launch_reduce(ctx->partials, nb, ctx->sums, slotD + n, s);
+        // checkpoint reset at (x_n, p_{n+1/2})
+        if (c.checkpoint_every > 0 && n > 0 && n % c.checkpoint_every == 0) {
+            const int slot = n / c.checkpoint_every - 1;
+            const float* ckd = ctx->ckpt + (size_t)slot * 6 * P;
+            launch_recon_err(ctx->disp, ckd, P, ctx->lat.inv_cell, ctx->partials, nb,
+                             ctx->maxbits + 2 + nck, s);
+            launch_reduce(ctx->partials, nb, ctx->sums, xCk + nck, s);
+            PM_TRY(copy_d2d(ctx, ctx->disp, ckd, vec));
+            PM_TRY(copy_d2d(ctx, ctx->mom, ckd + 3 * P, vec));
+            ++nck;
+        }
+        // recompute F(x_n); un-kick and (i) at x_n
+        compute_force(ctx, ctx->disp, sc.a[n]);
+        const double c0 = (n > 0 ? sc.kick_b[n - 1] : 0.0) + sc.kick_a[n];
+        {
+            KTimer t(ctx, PM_K_UNKICK_VJP, bytes_unkick);
+            launch_unkick_vjp(ctx->disp, ctx->mom, ctx->creal(1), ctx->creal_stride(), ctx->lat,
+                              (float)c0, ctx->pi, ctx->xi, ctx->partials, nb, 1, s);
+        }
+        launch_reduce(ctx->partials, nb, ctx->sums, slotS + n, s);
+    }
+    // (ii) + (iii) at x_0
+    vjp_mesh(ctx, ctx->disp, ctx->pi, (float)sc.kick_a[0], sc.a[0]);
+    launch_wgrad(ctx->creal(0), ctx->lat.rp, mass, ctx->disp, ctx->mom, ctx->xi, ctx->pi, nullptr,
+                 ctx->lat, 0.f, 2, nullptr, nb, s);
+
+    // ICs: x_0 = q + D0 s, p_0 = G0 s
+    ic_synthesis(ctx, ctx->radial_ic, ctx->s_ic, nullptr, nullptr);
+    launch_axpby(ctx->tmpv, ctx->s_ic, (float)sc.D0, nullptr, 0.f, 3 * P, s);
+    launch_recon_err(ctx->disp, ctx->tmpv, P, ctx->lat.inv_cell, ctx->partials, nb, ctx->maxbits, s);
+    launch_reduce(ctx->partials, nb, ctx->sums, xIc, s);
+    launch_axpby(ctx->tmpv, ctx->s_ic, (float)sc.G0, nullptr, 0.f, 3 * P, s);
+    launch_axpby(ctx->disp, ctx->mom, 1.f, ctx->tmpv, -1.f, 3 * P, s);   // p_0 error (disp reused)
+    launch_dot3(ctx->disp, ctx->disp, P, ctx->partials, nb, s);
+    launch_reduce(ctx->partials, nb, ctx->sums, xIcMom, s);
+    launch_dot3(ctx->tmpv, ctx->tmpv, P, ctx->partials, nb, s);
+    launch_reduce(ctx->partials, nb, ctx->sums, xIcMomRef, s);
+    launch_dot3(ctx->xi, ctx->s_ic, P, ctx->partials, nb, s);
+    launch_reduce(ctx->partials, nb, ctx->sums, xD0, s);
+    launch_dot3(ctx->pi, ctx->s_ic, P, ctx->partials, nb, s);
+    launch_reduce(ctx->partials, nb, ctx->sums, xG0, s);
+    // s_bar = D0 xi + G0 pi
+    launch_axpby(ctx->tmpv, ctx->xi, (float)sc.D0, ctx->pi, (float)sc.G0, 3 * P, s);
+    launch_dot3(ctx->tmpv, ctx->s_ic, P, ctx->partials, nb, s);
+    launch_reduce(ctx->partials, nb, ctx->sums, xSig, s);
+    ic_transpose(ctx, ctx->tmpv, g_noise);
+    // Omega_m dependence of P(k): s' = synthesis with d radial / d Omega_m
+    ic_synthesis(ctx, ctx->radial_ic_dom, ctx->xi, nullptr, nullptr);
+    launch_dot3(ctx->tmpv, ctx->xi, P, ctx->partials, nb, s);
+    launch_reduce(ctx->partials, nb, ctx->sums, xOm, s);
+    if (g_filter) PM_TRY(copy_d2d(ctx, g_filter, ctx->gtheta, kNParam * sizeof(float)));
+    hipEventRecord(ctx->ev[3], s);
+    PM_TRY(ctx->hip_check("pm_adjoint"));
+
+    // scalar results (synchronises)
+    const int nsum = 2 * N + 1 + kExtraSlots;
+    std::vector<double> h(nsum);
+    std::vector<unsigned> mb(kExtraSlots);
+    if (hipMemcpyAsync(h.data(), ctx->sums, nsum * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(mb.data(), ctx->maxbits, kExtraSlots * sizeof(unsigned), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return ctx->fail(PM_EHIP, "reading adjoint sums failed");
+    const Schedule& d = ctx->dsched;
+    double g_om = 0.0;
+    for (int n = 0; n < N; ++n)
+        g_om += h[slotS + n] * d.kick_a[n] + h[slotS + n + 1] * d.kick_b[n] + h[slotD + n] * d.drift[n];
+    g_om += h[xD0] * d.D0 + h[xG0] * d.G0 + h[xOm];
+    const double g_s8 = h[xSig] / ctx->cosmo.sigma8;
+    for (double v : h)
+        if (!std::isfinite(v)) return ctx->fail(PM_ENUMERIC, "non-finite adjoint sum");
+    if (g_cosmo) {
+        g_cosmo[0] = g_om;
+        g_cosmo[1] = g_s8;
+    }
+    auto as_float = [](unsigned b) {
+        float f;
+        std::memcpy(&f, &b, sizeof(f));
+        return (double)f;
+    };
+    ctx->stats.n_checkpoints = nck;
+    for (int k = 0; k < nck; ++k) {
+        ctx->stats.ckpt_rms_cells[k] = std::sqrt(h[xCk + k] / P);
+        ctx->stats.ckpt_max_cells[k] = as_float(mb[2 + k]);
+    }
+    ctx->stats.ic_rms_cells = std::sqrt(h[xIc] / P);
+    ctx->stats.ic_max_cells = as_float(mb[0]);
+    ctx->stats.ic_mom_rel_rms = h[xIcMomRef] > 0 ? std::sqrt(h[xIcMom] / h[xIcMomRef]) : 0.0;
+    return PM_OK;
+}
+
+int pm_loss_mse(pm_ctx* ctx, const float* dens, const float* target, float* g_dens,
+                double* loss) {
+    PM_TRY(ctx_check(ctx));
+    if (!dens || !target) return ctx->fail(PM_EINVAL, "dens and target are required");
+    const long n3 = (long)ctx->ng * ctx->ng * ctx->ng;
+    const int nb = particle_blocks(n3);
+    launch_mse(dens, target, g_dens, n3, ctx->partials, nb, ctx->stream);
+    PM_TRY(ctx->hip_check("pm_loss_mse"));
+    if (loss) {
+        launch_reduce(ctx->partials, nb, ctx->pkbins, 0, ctx->stream);
+        double v = 0.0;
+        if (hipMemcpyAsync(&v, ctx->pkbins, sizeof(double), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+            hipStreamSynchronize(ctx->stream) != hipSuccess)
+            return ctx->fail(PM_EHIP, "reading loss failed");
+        *loss = v / n3;
+    }
+    return PM_OK;
+}
+
+int pm_power_spectrum(pm_ctx* ctx, const float* dens, int32_t n_bins, double* k_out,
+                      double* pk_out, double* nmodes_out) {
+    PM_TRY(ctx_check(ctx));
+    if (!dens) return ctx->fail(PM_EINVAL, "dens is required");
+    if (n_bins < 1 || n_bins > ctx->ng) return ctx->fail(PM_EINVAL, "n_bins must be in [1, mesh]");
+    hipStream_t s = ctx->stream;
+    const int ng = ctx->ng;
+    launch_to_pitched(dens, ctx->creal(0), ng, ctx->lat.rp, 1.f, s);
+    launch_fft3_r2c(ctx->C[0], ng, ctx->cs, 1, ctx->plan.cplx_elems, ctx->tw, ng, s);
+    launch_zero(ctx->pkbins, 3 * (size_t)n_bins * sizeof(double), s);
+    launch_pk_bin(ctx->C[0], ng, ctx->cs, n_bins, ctx->pkbins, s);
+    PM_TRY(ctx->hip_check("pm_power_spectrum"));
+    std::vector<double> h(3 * (size_t)n_bins);
+    if (hipMemcpyAsync(h.data(), ctx->pkbins, h.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return ctx->fail(PM_EHIP, "reading P(k) failed");
+    const double L = ctx->cfg.box, n6 = std::pow((double)ng, 6.0);
+    for (int b = 0; b < n_bins; ++b) {
+        const double cnt = h[3 * b + 2];
+        if (k_out) k_out[b] = cnt > 0 ? h[3 * b + 1] / cnt * 2.0 * kPi / L : NAN;
+        if (pk_out) pk_out[b] = cnt > 0 ? h[3 * b] / cnt * L * L * L / n6 : NAN;
+        if (nmodes_out) nmodes_out[b] = cnt;
+    }
+    return PM_OK;
+}
+
+int pm_density(pm_ctx* ctx, const float* disp, float* dens) {
+    PM_TRY(ctx_check(ctx));
+    if (!disp || !dens) return ctx->fail(PM_EINVAL, "disp and dens are required");
+    launch_bin(disp, ctx->lat, ctx->bins, ctx->stream);
+    launch_scatter_density(disp, ctx->lat, ctx->bins, ctx->creal(0), ctx->stream);
+    launch_from_pitched(ctx->creal(0), dens, ctx->ng, ctx->lat.rp, ctx->stream);
+    return ctx->hip_check("pm_density");
+}
+
+int pm_force(pm_ctx* ctx, const float* disp, double a, float* force) {
+    PM_TRY(ctx_check(ctx));
+    if (!disp || !force) return ctx->fail(PM_EINVAL, "disp and force are required");
+    if (ctx->cfg.filter && !ctx->have_filter) return ctx->fail(PM_ESTATE, "pm_set_filter not called");
+    compute_force(ctx, disp, a);
+    launch_gather_force(disp, ctx->creal(1), ctx->creal_stride(), ctx->lat, force, ctx->stream);
+    return ctx->hip_check("pm_force");
+}
+
+int pm_force_vjp(pm_ctx* ctx, const float* disp, double a, const float* v, float* xi) {
+    PM_TRY(ctx_check(ctx));
+    if (!disp || !v || !xi) return ctx->fail(PM_EINVAL, "disp, v and xi are required");
+    if (ctx->cfg.filter && !ctx->have_filter) return ctx->fail(PM_ESTATE, "pm_set_filter not called");
+    hipStream_t s = ctx->stream;
+    const int nb = particle_blocks(ctx->P);
+    compute_force(ctx, disp, a);
+    launch_zero(xi, (size_t)ctx->P * 3 * sizeof(float), s);
+    launch_unkick_vjp(disp, nullptr, ctx->creal(1), ctx->creal_stride(), ctx->lat, 1.f, v, xi,
+                      nullptr, nb, 0, s);
+    if (ctx->cfg.filter) launch_zero(ctx->gtheta, kNParam * sizeof(float), s);
+    vjp_mesh(ctx, disp, v, 1.f, a);
+    launch_wgrad(ctx->creal(0), ctx->lat.rp, ctx->mass(), const_cast<float*>(disp), nullptr, xi,
+                 nullptr, nullptr, ctx->lat, 0.f, 2, nullptr, nb, s);
+    return ctx->hip_check("pm_force_vjp");
+}
+
+int pm_fft_r2c(pm_ctx* ctx, const float* real, float* spec) {
+    PM_TRY(ctx_check(ctx));
+    if (!real || !spec) return ctx->fail(PM_EINVAL, "real and spec are required");
+    hipStream_t s = ctx->stream;
+    const int ng = ctx->ng, h = ng / 2 + 1;
+    launch_to_pitched(real, ctx->creal(0), ng, ctx->lat.rp, 1.f, s);
+    launch_fft3_r2c(ctx->C[0], ng, ctx->cs, 1, ctx->plan.cplx_elems, ctx->tw, ng, s);
+    if (hipMemcpy2DAsync(spec, h * sizeof(float2), ctx->C[0], ctx->cs * sizeof(float2),
+                         h * sizeof(float2), (size_t)ng * ng, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return ctx->fail(PM_EHIP, "copy of the spectrum failed");
+    return ctx->hip_check("pm_fft_r2c");
+}
+
+int pm_fft_c2r(pm_ctx* ctx, const float* spec, float* real) {
+    PM_TRY(ctx_check(ctx));
+    if (!real || !spec) return ctx->fail(PM_EINVAL, "real and spec are required");
+    hipStream_t s = ctx->stream;
+    const int ng = ctx->ng, h = ng / 2 + 1;
+    if (hipMemcpy2DAsync(ctx->C[0], ctx->cs * sizeof(float2), spec, h * sizeof(float2),
+                         h * sizeof(float2), (size_t)ng * ng, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return ctx->fail(PM_EHIP, "copy of the spectrum failed");
+    launch_fft3_c2r(ctx->C[0], ng, ctx->cs, 1, ctx->plan.cplx_elems, ctx->tw, ng, s);
+    launch_from_pitched(ctx->creal(0), real, ng, ctx->lat.rp, s);
+    return ctx->hip_check("pm_fft_c2r");
+}
+
+int pm_filter_table(pm_ctx* ctx, double a, float* table) {
+    PM_TRY(ctx_check(ctx));
+    if (!table) return ctx->fail(PM_EINVAL, "table is required");
+    if (!ctx->cfg.filter || !ctx->have_filter) return ctx->fail(PM_ESTATE, "no filter weights set");
+    launch_mlp_table(ctx->theta, ctx->ng, (float)ctx->cfg.box, (float)a, 0.f, nullptr, table,
+                     ctx->stream);
+    return ctx->hip_check("pm_filter_table");
+}
+
+int pm_adam(pm_ctx* ctx, float* param, const float* grad, float* m, float* v, int32_t n,
+            double lr, double beta1, double beta2, double eps, int32_t t) {
+    PM_TRY(ctx_check(ctx));
+    if (!param || !grad || !m || !v || n < 1 || t < 1) return ctx->fail(PM_EINVAL, "bad Adam arguments");
+    const double bc1 = 1.0 - std::pow(beta1, t), bc2 = 1.0 - std::pow(beta2, t);
+    launch_adam(param, grad, m, v, n, (float)lr, (float)beta1, (float)beta2, (float)eps,
+                (float)bc1, (float)bc2, ctx->stream);
+    return ctx->hip_check("pm_adam");
+}
+
+int pm_stats_get(pm_ctx* ctx, pm_stats* out) {
+    PM_TRY(ctx_check(ctx));
+    if (!out) return ctx->fail(PM_EINVAL, "out is null");
+    float ms = 0.f;
+    if (hipEventSynchronize(ctx->ev[3]) == hipSuccess &&
+        hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]) == hipSuccess)
+        ctx->stats.adjoint_ms = ms;
+    if (hipEventSynchronize(ctx->ev[1]) == hipSuccess &&
+        hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess)
+        ctx->stats.forward_ms = ms;
+    ctx->flush_timing();
+    (void)hipGetLastError();
+    *out = ctx->stats;
+    return PM_OK;
+}
+
+int pm_stats_reset(pm_ctx* ctx) {
+    PM_TRY(ctx_check(ctx));
+    ctx->flush_timing();
+    for (int k = 0; k < PM_NKERNELS; ++k) {
+        ctx->stats.kernel_ms[k] = 0.0;
+        ctx->stats.kernel_launches[k] = 0;
+        ctx->stats.kernel_bytes[k] = 0.0;
+    }
+    return PM_OK;
+}
+
+void pm_destroy(pm_ctx* ctx) {
+    if (!ctx) return;
+    for (int k = 0; k < 4; ++k)
+        if (ctx->ev[k]) (void)hipEventDestroy(ctx->ev[k]);
+    for (hipEvent_t e : ctx->pool)
+        if (e) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+const char* pm_last_error(const pm_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_err.c_str();
+}
+
+}  // extern "C"

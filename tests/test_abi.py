@@ -1,0 +1,94 @@
+"""The C ABI without a GPU: symbols, host-side validation, host tables (pinned
+against the oracle's independent hypergeometric/quad implementation)."""
+import ctypes
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import cosmology as C
+from oracle import pm as opm
+from paper_2211_09958_amd import _lib, api
+from synthetic import SMALL, LARGE, MEDIUM, Cosmology
+
+CO = Cosmology()
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in _lib.EXPORTS:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    header = open(_lib.HERE + "/../include/pm.h").read()
+    import re
+    declared = set(re.findall(r"\b(pm_[a-z0-9_]+)\s*\(", header))
+    assert declared == set(_lib.EXPORTS)
+    assert declared <= exported
+
+
+@pytest.mark.parametrize("field,value", [("ptcl_grid", 48), ("mesh", 12), ("mesh", 2048),
+                                         ("box", -1.0), ("n_steps", 0), ("a_start", 0.0),
+                                         ("filter", 2), ("flags", 2), ("checkpoint_every", -1)])
+def test_invalid_config_rejected_on_host(field, value):
+    cfg = api.config_from_workload(SMALL)
+    setattr(cfg, field, value)
+    st = ctypes.c_int(0)
+    n = _lib.load().pm_workspace_bytes(ctypes.byref(cfg), ctypes.byref(st))
+    assert n == 0 and st.value == _lib.PM_EINVAL
+    assert _lib.load().pm_last_error(None)
+
+
+def test_mesh_must_be_multiple_of_particles():
+    cfg = api.make_config(64, 32, 64.0, 10)
+    with pytest.raises(_lib.PMError):
+        api.workspace_bytes(cfg)
+
+
+def test_pm_init_validates_before_touching_the_gpu():
+    lib = _lib.load()
+    cfg = api.config_from_workload(SMALL)
+    cs = api._cosmo_struct(CO)
+    out = ctypes.c_void_p()
+    assert lib.pm_init(ctypes.byref(cfg), ctypes.byref(cs), None, 0, None, ctypes.byref(out)) == _lib.PM_EINVAL
+    bad = api._cosmo_struct(CO)
+    bad.omega_m = -0.1
+    assert lib.pm_init(ctypes.byref(cfg), ctypes.byref(bad), ctypes.c_void_p(256), 10 ** 12, None,
+                       ctypes.byref(out)) == _lib.PM_EINVAL
+    # unaligned workspace
+    assert lib.pm_init(ctypes.byref(cfg), ctypes.byref(cs), ctypes.c_void_p(4), 10 ** 12, None,
+                       ctypes.byref(out)) == _lib.PM_EINVAL
+    # too small
+    assert lib.pm_init(ctypes.byref(cfg), ctypes.byref(cs), ctypes.c_void_p(256), 16, None,
+                       ctypes.byref(out)) == _lib.PM_ENOMEM
+    assert lib.pm_adjoint(None, None, None, None, None, None, None) == _lib.PM_EINVAL
+
+
+def test_workspace_scales_with_mesh_not_steps():
+    a = api.workspace_bytes(api.config_from_workload(MEDIUM))
+    b = api.workspace_bytes(api.config_from_workload(MEDIUM.with_(n_steps=630)))
+    assert 0 <= b - a < 1 << 20   # reverse-time adjoint: only scalar slots grow with steps
+    big = api.workspace_bytes(api.config_from_workload(LARGE))
+    assert big < 60e9
+
+
+@pytest.mark.parametrize("w", [SMALL, MEDIUM])
+def test_host_tables_match_oracle(w):
+    cfg = api.config_from_workload(w)
+    t = api.host_tables(cfg, CO)
+    co = C.kdk_coefficients(CO.omega_m, w.a_start, w.a_stop, w.n_steps)
+    np.testing.assert_allclose(t["kick_a"], co.kick_a, rtol=1e-11)
+    np.testing.assert_allclose(t["drift"], co.drift, rtol=1e-11)
+    np.testing.assert_allclose(t["kick_b"], co.kick_b, rtol=1e-11)
+    assert abs(t["D0"] / co.D0 - 1) < 1e-12 and abs(t["G0"] / co.G0 - 1) < 1e-11
+    np.testing.assert_allclose(t["D"], C.growth_D(co.a, CO.omega_m), rtol=1e-12)
+    np.testing.assert_allclose(t["G"], C.growth_G(co.a, CO.omega_m), rtol=1e-11)
+    d = C.kdk_coefficient_derivatives(CO.omega_m, w.a_start, w.a_stop, w.n_steps)
+    for key, ref in (("d_kick_a", d.kick_a), ("d_drift", d.drift), ("d_kick_b", d.kick_b)):
+        np.testing.assert_allclose(t[key], ref, rtol=1e-6, atol=1e-8 * np.abs(ref).max())
+    assert abs(t["d_D0"] / d.D0 - 1) < 1e-6
+    nsq = np.arange(t["pk"].size)
+    ref = C.linear_pk(2 * np.pi / w.box * np.sqrt(nsq), CO)
+    np.testing.assert_allclose(t["pk"][1:], ref[1:], rtol=1e-9)
+    assert t["pk"][0] == 0.0

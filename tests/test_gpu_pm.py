@@ -1,0 +1,192 @@
+"""End-to-end GPU parity: forward run, reverse-time adjoint, gradients, filter."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import CO, context, ctx_for, dev, host, periodic_cells, rel_l2, setup_for
+from oracle import mesh as M
+from oracle import mlp as omlp
+from oracle import pm as opm
+from paper_2211_09958_amd import api
+from synthetic import SMALL, Workload, mlp_init, normal, white_noise
+
+pytestmark = pytest.mark.gpu
+
+TINY = Workload("tiny", ptcl_grid=8, mesh=16, box=32.0, n_steps=4)
+
+
+@pytest.fixture(scope="module")
+def small_runs():
+    noise = white_noise(SMALL.ptcl_grid, 0)
+    run = opm.forward(noise, setup_for(SMALL))
+    pm = ctx_for(SMALL)
+    disp, mom, dens = pm.forward(dev(noise))
+    return noise, run, host(disp), host(mom), host(dens)
+
+
+def test_small_positions_within_1e3_cells(small_runs):
+    noise, run, disp, mom, dens = small_runs
+    d = periodic_cells(disp, run.disp[-1], SMALL.box, SMALL.mesh)
+    rms = float(np.sqrt(np.mean(d * d)))
+    print(f"position RMS {rms:.3e} cells, max {d.max():.3e}")
+    assert rms < 1e-3
+
+
+def test_small_power_spectrum_within_1e4(small_runs):
+    noise, run, disp, mom, dens = small_runs
+    k, P, N = ctx_for(SMALL).power_spectrum(dev(dens), SMALL.mesh // 2)
+    kr, Pr, Nr = M.power_spectrum(run.dens, SMALL.box, SMALL.mesh // 2)
+    k_nyq = np.pi * SMALL.mesh / SMALL.box
+    sel = kr < 0.5 * k_nyq
+    err = np.abs(P[sel] / Pr[sel] - 1)
+    print("P(k) relative errors", err.max())
+    assert err.max() < 1e-4
+
+
+def test_small_momentum_and_density(small_runs):
+    noise, run, disp, mom, dens = small_runs
+    assert rel_l2(mom, run.mom) < 1e-3
+    assert np.max(np.abs(dens - run.dens)) < 5e-2 * np.abs(run.dens).max()
+
+
+def test_forward_bitwise_repeatable():
+    pm = ctx_for(TINY)
+    n = dev(white_noise(8, 5))
+    a = pm.forward(n)
+    b = pm.forward(n)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+def _grad_case(w, seed_run, seed_tgt, theta=None):
+    st = setup_for(w)
+    noise = white_noise(w.ptcl_grid, seed_run)
+    target = opm.forward(white_noise(w.ptcl_grid, seed_tgt), st).dens
+    run = opm.forward(noise, st, theta)
+    _, gd = opm.mse_loss(run.dens, target)
+    P = w.ptcl_grid ** 3
+    gdisp, gmom = normal((P, 3), 9) * 1e-3, normal((P, 3), 10) * 1e-3
+    ref = opm.adjoint(run, noise, g_dens=gd, g_disp=gdisp, g_mom=gmom)
+    return noise, target, gdisp, gmom, ref
+
+
+def omega_m_scale(w, ref):
+    """Sum of |terms| of dL/dOmega_m in the oracle's decomposition."""
+    from oracle import cosmology as C
+    d = C.kdk_coefficient_derivatives(CO.omega_m, w.a_start, w.a_stop, w.n_steps)
+    terms = [np.abs(ref.kick_a * d.kick_a).sum(), np.abs(ref.kick_b * d.kick_b).sum(),
+             np.abs(ref.drift * d.drift).sum(), abs(ref.D0 * d.D0), abs(ref.G0 * d.G0)]
+    ic = ref.omega_m - (np.dot(ref.kick_a, d.kick_a) + np.dot(ref.kick_b, d.kick_b)
+                        + np.dot(ref.drift, d.drift) + ref.D0 * d.D0 + ref.G0 * d.G0)
+    return float(sum(terms) + abs(ic))
+
+
+@pytest.mark.parametrize("w", [TINY, SMALL])
+def test_gradients_match_oracle(w):
+    noise, target, gdisp, gmom, ref = _grad_case(w, 3, 4)
+    pm = ctx_for(w)
+    disp, mom, dens = pm.forward(dev(noise))
+    L, gd = pm.loss_mse(dens, dev(target))
+    g_noise, (g_om, g_s8), _ = pm.adjoint(gd, dev(gdisp), dev(gmom))
+    e_noise = rel_l2(host(g_noise), ref.noise)
+    # dL/dOmega_m is a sum of terms that largely cancel; FP32 rounding scales
+    # with the sum of their magnitudes, so the error is measured against it
+    e_om = abs(g_om - ref.omega_m) / omega_m_scale(w, ref)
+    e_s8 = abs(g_s8 / ref.sigma8 - 1)
+    print(f"{w.name}: noise {e_noise:.2e} Om {e_om:.2e} (plain rel "
+          f"{abs(g_om / ref.omega_m - 1):.2e}) s8 {e_s8:.2e}")
+    assert e_noise < 1e-3 and e_om < 1e-3 and e_s8 < 1e-3
+
+
+@pytest.mark.parametrize("w", [TINY, SMALL])
+def test_reverse_time_reconstruction(w):
+    pm = ctx_for(w)
+    pm.forward(dev(white_noise(w.ptcl_grid, 1)))
+    pm.adjoint(g_disp=dev(np.zeros((w.ptcl_grid ** 3, 3))))
+    st = pm.stats()
+    print(w.name, st["ic_rms_cells"], st["ic_max_cells"], st["ic_mom_rel_rms"])
+    assert st["ic_rms_cells"] < 1e-4
+
+
+def test_checkpointed_adjoint_matches_pure():
+    w = SMALL
+    noise, target, gdisp, gmom, ref = _grad_case(w, 5, 6)
+    out = []
+    for ck in (0, 3):
+        pm = context(w.ptcl_grid, w.mesh, w.box, w.n_steps, checkpoint_every=ck)
+        disp, mom, dens = pm.forward(dev(noise))
+        _, gd = pm.loss_mse(dens, dev(target))
+        out.append(pm.adjoint(gd, dev(gdisp), dev(gmom)))
+        if ck:
+            st = pm.stats()
+            assert st["n_checkpoints"] == 3
+            assert max(st["ckpt_rms_cells"]) < 1e-4
+    assert rel_l2(host(out[1][0]), host(out[0][0])) < 1e-4
+    assert abs(out[1][1][0] / out[0][1][0] - 1) < 1e-4
+
+
+def test_autograd_function():
+    w = TINY
+    pm = ctx_for(w)
+    noise = dev(white_noise(8, 2)).requires_grad_(True)
+    om = torch.tensor(CO.omega_m, dtype=torch.float64, requires_grad=True)
+    s8 = torch.tensor(CO.sigma8, dtype=torch.float64, requires_grad=True)
+    disp, mom, dens = api.simulate(pm, noise, om, s8)
+    loss = (dens.double() ** 2).mean()
+    loss.backward()
+    run = opm.forward(white_noise(8, 2), setup_for(w))
+    ref = opm.adjoint(run, white_noise(8, 2), g_dens=2 * run.dens / run.dens.size)
+    assert rel_l2(host(noise.grad), ref.noise) < 1e-3
+    assert abs(float(om.grad) / ref.omega_m - 1) < 1e-3
+
+
+# ---------------------------------------------------------------- filter
+
+def test_filter_table_matches_oracle():
+    pm = context(8, 32, 32.0, 2, filter=True)
+    theta = mlp_init(1, zero_last=False)
+    pm.set_filter(dev(theta))
+    for a in (0.1, 0.7):
+        got = host(pm.filter_table(a))
+        ref, _ = omlp.filter_table(theta, 32, 32.0, a)
+        assert np.max(np.abs(got - ref)) < 2e-5 * np.abs(ref).max()
+
+
+def test_zero_last_layer_reproduces_plain_pm_bitwise():
+    plain = ctx_for(TINY)
+    filt = context(TINY.ptcl_grid, TINY.mesh, TINY.box, TINY.n_steps, filter=True)
+    filt.set_filter(dev(mlp_init(0)))
+    n = dev(white_noise(8, 7))
+    a, b = plain.forward(n), filt.forward(n)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+def test_filter_gradients_match_oracle():
+    w = TINY
+    theta = 0.5 * mlp_init(0, zero_last=False)
+    noise, target, gdisp, gmom, ref = _grad_case(w, 3, 4, theta)
+    pm = context(w.ptcl_grid, w.mesh, w.box, w.n_steps, filter=True)
+    pm.set_filter(dev(theta))
+    disp, mom, dens = pm.forward(dev(noise))
+    _, gd = pm.loss_mse(dens, dev(target))
+    g_noise, (g_om, g_s8), g_w = pm.adjoint(gd, dev(gdisp), dev(gmom), want_filter=True)
+    e_w = rel_l2(host(g_w), ref.theta)
+    e_n = rel_l2(host(g_noise), ref.noise)
+    print(f"filter grads: W {e_w:.2e} noise {e_n:.2e}")
+    assert e_w < 1e-3 and e_n < 1e-3
+
+
+def test_adam_matches_torch():
+    pm = ctx_for(TINY)
+    p0 = normal(100, 1).astype(np.float32)
+    p = dev(p0)
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    ref = torch.nn.Parameter(torch.tensor(p0, dtype=torch.float64))
+    opt = torch.optim.Adam([ref], lr=1e-2)
+    for t in range(1, 6):
+        g = normal(100, 10 + t).astype(np.float32)
+        pm.adam(p, dev(g), m, v, t, lr=1e-2)
+        ref.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+    np.testing.assert_allclose(host(p), ref.detach().numpy(), rtol=1e-5, atol=1e-6)
