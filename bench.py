@@ -43,6 +43,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-pure-variant", action="store_true")
     p.add_argument("--cpu-only", action="store_true", help="only the oracle CPU baseline")
+    p.add_argument("--calib-copy-gib", type=float, default=0.0,
+                   help="also run one device copy of this many GiB (HBM counter calibration)")
     return p.parse_args()
 
 
@@ -124,6 +126,13 @@ def main():
         g_noise, g_cosmo, _ = ctx.adjoint(g_dens=g)
         return g_cosmo
 
+    if args.calib_copy_gib > 0:
+        n = int(args.calib_copy_gib * 2 ** 30) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step(pm)
     torch.cuda.synchronize()

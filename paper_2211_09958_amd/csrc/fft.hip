@@ -17,6 +17,7 @@
 
 #include "fft_engine.h"
 #include "kernels.h"
+#include "xcd.h"
 
 namespace pmx {
 namespace {
@@ -41,7 +42,7 @@ k_fft_x_r2c(float2* __restrict__ buf, int cs, long nrows, long bufStride,
     constexpr int LS = H + 1;
     __shared__ float2 lds[ROWS * LS];
     const int r = threadIdx.x / T, j = threadIdx.x % T;
-    const long row = (long)blockIdx.x * ROWS + r;
+    const long row = (long)xcd_block(blockIdx.x, gridDim.x) * ROWS + r;
     const bool valid = row < nrows;
     float2* rowp = buf + blockIdx.y * bufStride + (valid ? row : 0) * cs;
     const int twH = ntw / H, twN = ntw / N;
@@ -76,7 +77,7 @@ k_fft_x_c2r(float2* __restrict__ buf, int cs, long nrows, long bufStride,
     constexpr int LS = H + 1;
     __shared__ float2 lds[ROWS * LS];
     const int r = threadIdx.x / T, j = threadIdx.x % T;
-    const long row = (long)blockIdx.x * ROWS + r;
+    const long row = (long)xcd_block(blockIdx.x, gridDim.x) * ROWS + r;
     const bool valid = row < nrows;
     float2* rowp = buf + blockIdx.y * bufStride + (valid ? row : 0) * cs;
     const int twH = ntw / H, twN = ntw / N;
@@ -111,7 +112,8 @@ k_fft_strided(float2* __restrict__ buf, long S, long A, int ncb, long bufStride,
     constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::W;
     __shared__ float2 lds[H * W];
     const int c = threadIdx.x % W, j = threadIdx.x / W;
-    const int a = blockIdx.x / ncb, cb = blockIdx.x % ncb;
+    const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int a = tile / ncb, cb = tile % ncb;
     float2* base = buf + blockIdx.y * bufStride + a * A + cb * W + c;
     float2 v[E];
 #pragma unroll
@@ -132,7 +134,8 @@ k_grad_z(const float2* __restrict__ src, float2* __restrict__ dst, long dstStrid
     constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::W, n = H;
     __shared__ float2 lds[H * W];
     const int c = threadIdx.x % W, j = threadIdx.x / W;
-    const int i1 = blockIdx.x / ncb, cb = blockIdx.x % ncb;
+    const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int i1 = tile / ncb, cb = tile % ncb;
     const int k2 = cb * W + c;
     const long S = (long)n * cs;
     const long col = (long)i1 * cs + k2;
@@ -181,7 +184,8 @@ k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
     constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::W, n = H;
     __shared__ float2 lds[H * W];
     const int c = threadIdx.x % W, j = threadIdx.x / W;
-    const int i1 = blockIdx.x / ncb, cb = blockIdx.x % ncb;
+    const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int i1 = tile / ncb, cb = tile % ncb;
     const int k2 = cb * W + c;
     const long S = (long)n * cs;
     const long col = (long)i1 * cs + k2;

@@ -45,12 +45,24 @@ void launch_fft3_c2r(float2* buf, int n, int cs, int nbuf, long bufStride, const
                      int ntw, hipStream_t s);
 
 // ---------------------------------------------------------------- particles
+// Particle state is fixed point so that kick and drift are exactly invertible:
+// positions x are uint32 in units of box / 2^32 (periodic wrap is integer
+// overflow; a mesh cell is 2^shift units), momenta are int32 in units of
+// mom_unit = cell * 2^-22 (range +-512 cells per unit time).
 struct Lattice {
-    int np;          // particles per side
-    int ng;          // mesh cells per side
-    int ratio;       // ng / np
-    float inv_cell;  // ng / box
-    long rp;         // real-row pitch of meshes (floats)
+    int np;            // particles per side
+    int ng;            // mesh cells per side
+    int ratio;         // ng / np
+    float inv_cell;    // ng / box
+    long rp;           // real-row pitch of meshes (floats)
+    int shift;         // 32 - log2(ng)
+    uint32_t half;     // half a cell in position units
+    uint32_t qstep;    // lattice spacing in position units (2^32 / np)
+    float frac;        // 2^-shift
+    float len_to_pos;  // 2^32 / box
+    float pos_to_len;  // box / 2^32
+    float mom_unit;    // momentum per integer unit
+    float inv_mom_unit;
 };
 
 struct Bins {
@@ -69,34 +81,40 @@ int choose_tile(int ng);
 long scan_tmp_elems(long nkeys);
 
 // Counting sort of particles by (tile of the CIC base cell, spill class).
-void launch_bin(const float* disp, const Lattice& L, Bins& b, hipStream_t s);
+void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, hipStream_t s);
 // Density delta = rho - 1 (particle mass (ng/np)^3) into a real mesh with pitch
 // L.rp; every cell written once (no pre-zeroing), deterministic.
-void launch_scatter_density(const float* disp, const Lattice& L, const Bins& b, float* mesh,
+void launch_scatter_density(const uint32_t* xq, const Lattice& L, const Bins& b, float* mesh,
                             hipStream_t s);
 // out_j = Sum_p coeff v_{p,j} w(x_p, node) for j = 0..2 into meshes out + j*outStride.
-void launch_scatter_vec(const float* disp, const float* v, float coeff, const Lattice& L,
+void launch_scatter_vec(const uint32_t* xq, const float* v, float coeff, const Lattice& L,
                         const Bins& b, float* out, long outStride, hipStream_t s);
 
 // Forward gather-kick-drift: F = gather(force meshes), p += kick F, then
-// optional checkpoint copy of (s, p), then s += drift p (if do_drift).
-void launch_gather_kick_drift(float* disp, float* mom, const float* fmesh, long fStride,
+// optional checkpoint copy of (x, p), then x += drift p (if do_drift).
+void launch_gather_kick_drift(uint32_t* xq, int32_t* pq, const float* fmesh, long fStride,
                               const Lattice& L, float kick, float drift, int do_drift,
-                              float* ck_disp, float* ck_mom, hipStream_t s);
+                              uint32_t* ck_x, int32_t* ck_p, hipStream_t s);
 // Gather the force only: out[p][j] = Sum w F_j.
-void launch_gather_force(const float* disp, const float* fmesh, long fStride, const Lattice& L,
+void launch_gather_force(const uint32_t* xq, const float* fmesh, long fStride, const Lattice& L,
                          float* out, hipStream_t s);
-// Reverse step part 1 at x: F = gather; p -= coeff F; xi += Sum_j coeff pi_j grad w . F~_j;
-// block partials of Sum pi . F (FP64).  pi may be null (then only the un-kick).
-void launch_unkick_vjp(const float* disp, float* mom, const float* fmesh, long fStride,
+// Reverse step part 1 at x: F = gather; p -= coeff F (exact inverse of the
+// forward kick); xi += Sum_j coeff pi_j grad w . F~_j; block partials of
+// Sum pi . F (FP64).  pq may be null (no un-kick), pi may be null.
+void launch_unkick_vjp(const uint32_t* xq, int32_t* pq, const float* fmesh, long fStride,
                        const Lattice& L, float coeff, const float* pi, float* xi,
-                       double* partials, int nblocks, int do_unkick, hipStream_t s);
+                       double* partials, int nblocks, hipStream_t s);
 // xi (+)= g_scale * Sum grad w . mesh (mesh pitch given); mode 0: xi = base + g
 // (base nullable); mode 1: xi += g, partial Sum xi . p, pi += drift xi,
-// s -= drift p; mode 2: xi += g.
-void launch_wgrad(const float* mesh, long pitch, float g_scale, float* disp, const float* mom,
+// x -= drift p (exact inverse of the forward drift); mode 2: xi += g.
+void launch_wgrad(const float* mesh, long pitch, float g_scale, uint32_t* xq, const int32_t* pq,
                   float* xi, float* pi, const float* base, const Lattice& L, float drift,
                   int mode, double* partials, int nblocks, hipStream_t s);
+// Displacements (float, Mpc/h) -> fixed-point positions q + s.
+void launch_to_fixed(const float* disp, uint32_t* xq, const Lattice& L, hipStream_t s);
+// Fixed-point state -> displacement (minimum image of x - q) and momentum.
+void launch_from_fixed(const uint32_t* xq, const int32_t* pq, const Lattice& L, float* disp,
+                       float* mom, hipStream_t s);
 int particle_blocks(long P);
 
 // Dot products over [P][3] arrays into FP64 block partials.
@@ -104,14 +122,21 @@ void launch_dot3(const float* a, const float* b, long P, double* partials, int n
                  hipStream_t s);
 // sums[slot] = Sum of partials[0..nblocks)
 void launch_reduce(const double* partials, int nblocks, double* sums, int slot, hipStream_t s);
-// Reconstruction error of displacements in cells: sums[slot] = Sum |a-b|^2,
-// maxbits[slot] (as float bits) = max |a-b| component-wise Euclidean.
-void launch_recon_err(const float* a, const float* b, long P, float inv_cell, double* partials,
+// Reconstruction error of fixed-point positions in cells: partials of
+// Sum |a-b|^2 (minimum image), *maxbits (as float bits) = max |a-b|.
+void launch_recon_err(const uint32_t* a, const uint32_t* b, const Lattice& L, double* partials,
                       int nblocks, unsigned* maxbits, hipStream_t s);
 
-// ICs: disp = D0 s, mom = G0 s from three real meshes (pitch rp) on the lattice.
-void launch_ic_state(const float* smesh, long sStride, int np, long rp, float D0, float G0,
-                     float* disp, float* mom, float* s_out, hipStream_t s);
+// Zel'dovich state from three real meshes s_j (pitch rp, on the particle
+// lattice): x = q + D0 s, p = G0 s in fixed point (xq, pq nullable), s_out
+// (nullable) = s.  launch_ic_check instead compares that state with the given
+// xq/pq: block partials of Sum|dx|^2 (cells^2), Sum|dp|^2 and Sum|p|^2 at
+// partials[0, nblocks, 2 nblocks) and max |dx| (cells) into *maxbits.
+void launch_ic_state(const float* smesh, long sStride, long rp, float D0, float G0,
+                     const Lattice& L, uint32_t* xq, int32_t* pq, float* s_out, hipStream_t s);
+void launch_ic_check(const float* smesh, long sStride, long rp, float D0, float G0,
+                     const Lattice& L, const uint32_t* xq, const int32_t* pq, double* partials,
+                     int nblocks, unsigned* maxbits, hipStream_t s);
 // Compact [n]^3 <-> pitched rows.
 void launch_to_pitched(const float* src, float* dst, int n, long rp, float scale,
                        hipStream_t s);

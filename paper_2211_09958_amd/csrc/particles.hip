@@ -6,9 +6,15 @@
 // node is the product over the three axes.  Assignment (scatter) and
 // interpolation (gather) use the same weights, so one is the transpose of the
 // other; the weight's derivative is +-1/cell along the axis times the other two
-// factors.  Positions are kept as displacements s from the lattice point q, and
-// u is formed as j*(ng/np) + (s/cell - 1/2) so that the fractional part keeps
-// the precision of s.
+// factors.
+//
+// State is fixed point (see kernels.h): positions are uint32 in units of
+// box/2^32, so the base node is the top log2(ng) bits of x - cell/2 and t is
+// read exactly from the low bits; momenta are int32.  The kick and drift add
+// integer increments rounded from FP32 products by the shared helpers below,
+// and the force is bitwise reproducible for a given state, so the reverse-time
+// pass subtracts exactly what the forward pass added: the trajectory is
+// recovered bit for bit.
 //
 // Bins: particles are counting-sorted by the T^3-cell tile holding their base
 // node and by a 3-bit "spill class" (bit a set when the base node is on the
@@ -23,6 +29,7 @@
 #include <type_traits>
 
 #include "kernels.h"
+#include "xcd.h"
 
 namespace pmx {
 namespace {
@@ -37,18 +44,27 @@ __device__ __forceinline__ void lattice_index(long p, int np, int jj[3]) {
     jj[0] = (int)(q / np);
 }
 
-// Base node index (wrapped) and fractional offset per axis.
-__device__ __forceinline__ void locate(const float* __restrict__ s3, long p, const Lattice& L,
-                                       int ii[3], float t[3]) {
-    int jj[3];
-    lattice_index(p, L.np, jj);
+// Base node index and fractional offset per axis from fixed-point positions.
+__device__ __forceinline__ void locate(const uint32_t* __restrict__ x3, const Lattice& L, int ii[3],
+                                       float t[3]) {
+    const uint32_t mask = (1u << L.shift) - 1u;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        float sc = s3[a] * L.inv_cell - 0.5f;
-        float fl = floorf(sc);
-        t[a] = sc - fl;
-        ii[a] = (jj[a] * L.ratio + (int)fl) & (L.ng - 1);
+        const uint32_t u = x3[a] - L.half;
+        ii[a] = (int)(u >> L.shift);
+        t[a] = (float)(u & mask) * L.frac;
     }
+}
+
+// Integer momentum increment of a kick by coeff * F (forward adds, reverse subtracts).
+__device__ __forceinline__ int32_t kick_units(float coeff, float F, const Lattice& L) {
+    return __float2int_rn(__fmul_rn(__fmul_rn(coeff, F), L.inv_mom_unit));
+}
+
+// Integer position increment of a drift by coeff * p, wrapped modulo the box.
+__device__ __forceinline__ uint32_t drift_units(float coeff, int32_t pq, const Lattice& L) {
+    const float d = __fmul_rn(__fmul_rn(coeff, __fmul_rn((float)pq, L.mom_unit)), L.len_to_pos);
+    return (uint32_t)__float2ll_rn(d);
 }
 
 __device__ __forceinline__ double block_sum(double v) {
@@ -67,16 +83,16 @@ __device__ __forceinline__ double block_sum(double v) {
 // ------------------------------------------------------------- binning
 
 __global__ void __launch_bounds__(kBlock)
-k_bin_count(const float* __restrict__ disp, Lattice L, int tile, int nt, long P,
+k_bin_count(const uint32_t* __restrict__ xq, Lattice L, int tile, int nt, long P,
             uint32_t* __restrict__ counts, uint32_t* __restrict__ keys,
             uint32_t* __restrict__ ranks) {
-    const long i = (long)blockIdx.x * kBlock + threadIdx.x;
+    const long i = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const bool valid = i < P;
     uint32_t key = 0xffffffffu;
     if (valid) {
         int ii[3];
         float t[3];
-        locate(disp + 3 * i, i, L, ii, t);
+        locate(xq + 3 * i, L, ii, t);
         uint32_t tix = ((uint32_t)(ii[0] / tile) * nt + (uint32_t)(ii[1] / tile)) * nt +
                        (uint32_t)(ii[2] / tile);
         uint32_t cls = ((ii[0] % tile == tile - 1) << 2) | ((ii[1] % tile == tile - 1) << 1) |
@@ -179,7 +195,7 @@ k_scan_add(uint32_t* __restrict__ out, long n, const uint32_t* __restrict__ bsum
 __global__ void __launch_bounds__(kBlock)
 k_bin_permute(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ ranks,
               const uint32_t* __restrict__ offsets, long P, uint32_t* __restrict__ perm) {
-    const long i = (long)blockIdx.x * kBlock + threadIdx.x;
+    const long i = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i < P) perm[offsets[keys[i]] + ranks[i]] = (uint32_t)i;
 }
 
@@ -218,7 +234,7 @@ constexpr int kRanges = 20;
 
 template <int T, bool VEC>
 __global__ void __launch_bounds__(kBlock)
-k_scatter_tile(const float* __restrict__ disp, const float* __restrict__ vals, float coeff,
+k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, float coeff,
                Lattice L, int nt, const uint32_t* __restrict__ offsets,
                const uint32_t* __restrict__ perm, float* __restrict__ out, long outStride) {
     constexpr int T3 = T * T * T;
@@ -226,7 +242,7 @@ k_scatter_tile(const float* __restrict__ disp, const float* __restrict__ vals, f
     using Acc = typename std::conditional<VEC, float, unsigned long long>::type;
     __shared__ Acc acc[NACC * T3];
     __shared__ uint32_t rs[kRanges], re[kRanges];
-    const int tile = blockIdx.x;
+    const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
     const int tz = tile % nt, ty = (tile / nt) % nt, tx = tile / (nt * nt);
     const int lo[3] = {tx * T, ty * T, tz * T};
     for (int c = threadIdx.x; c < NACC * T3; c += kBlock) acc[c] = (Acc)0;
@@ -240,7 +256,7 @@ k_scatter_tile(const float* __restrict__ disp, const float* __restrict__ vals, f
             const long p = perm[idx];
             int ii[3];
             float t[3];
-            locate(disp + 3 * p, p, L, ii, t);
+            locate(xq + 3 * p, L, ii, t);
             float v0 = 0.f, v1 = 0.f, v2 = 0.f;
             if constexpr (VEC) {
                 v0 = coeff * vals[3 * p];
@@ -315,66 +331,71 @@ __device__ __forceinline__ void nodes8(const int ii[3], const float t[3], const 
         const float a1 = c1 ? t[1] : 1.f - t[1];
         const float a2 = c2 ? t[2] : 1.f - t[2];
         const float d0 = c0 ? ic : -ic, d1 = c1 ? ic : -ic, d2 = c2 ? ic : -ic;
-        n.w[c] = a0 * a1 * a2;
+        n.w[c] = __fmul_rn(__fmul_rn(a0, a1), a2);
         n.g[c][0] = d0 * a1 * a2;
         n.g[c][1] = a0 * d1 * a2;
         n.g[c][2] = a0 * a1 * d2;
     }
 }
 
+// F_j = Sum_c w_c F~_j(node c), with explicitly rounded operations so that the
+// forward gather and the reverse-time re-gather agree bit for bit.
+__device__ __forceinline__ void gather3(const Node8& n, const float* __restrict__ fm, long fStride,
+                                        float F[3]) {
+    F[0] = F[1] = F[2] = 0.f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        F[0] = __fmaf_rn(n.w[c], fm[n.idx[c]], F[0]);
+        F[1] = __fmaf_rn(n.w[c], fm[fStride + n.idx[c]], F[1]);
+        F[2] = __fmaf_rn(n.w[c], fm[2 * fStride + n.idx[c]], F[2]);
+    }
+}
+
 __global__ void __launch_bounds__(kBlock)
-k_gather_kick_drift(float* __restrict__ disp, float* __restrict__ mom,
+k_gather_kick_drift(uint32_t* __restrict__ xq, int32_t* __restrict__ pq,
                     const float* __restrict__ fm, long fStride, Lattice L, long P, float kick,
-                    float drift, int do_drift, float* __restrict__ ck_disp,
-                    float* __restrict__ ck_mom) {
-    for (long p = (long)blockIdx.x * kBlock + threadIdx.x; p < P; p += (long)gridDim.x * kBlock) {
-        float s[3] = {disp[3 * p], disp[3 * p + 1], disp[3 * p + 2]};
+                    float drift, int do_drift, uint32_t* __restrict__ ck_x,
+                    int32_t* __restrict__ ck_p) {
+    for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
+         p += (long)gridDim.x * kBlock) {
+        uint32_t x[3] = {xq[3 * p], xq[3 * p + 1], xq[3 * p + 2]};
         int ii[3];
         float t[3];
-        locate(s, p, L, ii, t);
+        locate(x, L, ii, t);
         Node8 n;
         nodes8(ii, t, L, n);
-        float F[3] = {0.f, 0.f, 0.f};
+        float F[3];
+        gather3(n, fm, fStride, F);
+        int32_t m[3];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            F[0] += n.w[c] * fm[n.idx[c]];
-            F[1] += n.w[c] * fm[fStride + n.idx[c]];
-            F[2] += n.w[c] * fm[2 * fStride + n.idx[c]];
-        }
-        float m[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) m[a] = mom[3 * p + a] + kick * F[a];
-        if (ck_disp) {
+        for (int a = 0; a < 3; ++a) m[a] = pq[3 * p + a] + kick_units(kick, F[a], L);
+        if (ck_x) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                ck_disp[3 * p + a] = s[a];
-                ck_mom[3 * p + a] = m[a];
+                ck_x[3 * p + a] = x[a];
+                ck_p[3 * p + a] = m[a];
             }
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            mom[3 * p + a] = m[a];
-            if (do_drift) disp[3 * p + a] = s[a] + drift * m[a];
+            pq[3 * p + a] = m[a];
+            if (do_drift) xq[3 * p + a] = x[a] + drift_units(drift, m[a], L);
         }
     }
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_gather_force(const float* __restrict__ disp, const float* __restrict__ fm, long fStride,
+k_gather_force(const uint32_t* __restrict__ xq, const float* __restrict__ fm, long fStride,
                Lattice L, long P, float* __restrict__ out) {
-    for (long p = (long)blockIdx.x * kBlock + threadIdx.x; p < P; p += (long)gridDim.x * kBlock) {
+    for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
+         p += (long)gridDim.x * kBlock) {
         int ii[3];
         float t[3];
-        locate(disp + 3 * p, p, L, ii, t);
+        locate(xq + 3 * p, L, ii, t);
         Node8 n;
         nodes8(ii, t, L, n);
-        float F[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            F[0] += n.w[c] * fm[n.idx[c]];
-            F[1] += n.w[c] * fm[fStride + n.idx[c]];
-            F[2] += n.w[c] * fm[2 * fStride + n.idx[c]];
-        }
+        float F[3];
+        gather3(n, fm, fStride, F);
         out[3 * p] = F[0];
         out[3 * p + 1] = F[1];
         out[3 * p + 2] = F[2];
@@ -382,33 +403,35 @@ k_gather_force(const float* __restrict__ disp, const float* __restrict__ fm, lon
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_unkick_vjp(const float* __restrict__ disp, float* __restrict__ mom, const float* __restrict__ fm,
-             long fStride, Lattice L, long P, float coeff, const float* __restrict__ pi,
-             float* __restrict__ xi, double* __restrict__ partials, int do_unkick) {
+k_unkick_vjp(const uint32_t* __restrict__ xq, int32_t* __restrict__ pq,
+             const float* __restrict__ fm, long fStride, Lattice L, long P, float coeff,
+             const float* __restrict__ pi, float* __restrict__ xi, double* __restrict__ partials) {
     double acc = 0.0;
-    for (long p = (long)blockIdx.x * kBlock + threadIdx.x; p < P; p += (long)gridDim.x * kBlock) {
+    for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
+         p += (long)gridDim.x * kBlock) {
         int ii[3];
         float t[3];
-        locate(disp + 3 * p, p, L, ii, t);
+        locate(xq + 3 * p, L, ii, t);
         Node8 n;
         nodes8(ii, t, L, n);
-        float F[3] = {0.f, 0.f, 0.f}, G[3][3] = {{0.f}};
+        float F[3];
+        gather3(n, fm, fStride, F);
+        if (pq) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const float f = fm[j * fStride + n.idx[c]];
-                F[j] += n.w[c] * f;
-                G[j][0] += n.g[c][0] * f;
-                G[j][1] += n.g[c][1] * f;
-                G[j][2] += n.g[c][2] * f;
-            }
-        }
-        if (do_unkick) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) mom[3 * p + a] -= coeff * F[a];
+            for (int a = 0; a < 3; ++a) pq[3 * p + a] -= kick_units(coeff, F[a], L);
         }
         if (pi) {
+            float G[3][3] = {{0.f}};
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const float f = fm[j * fStride + n.idx[c]];
+                    G[j][0] += n.g[c][0] * f;
+                    G[j][1] += n.g[c][1] * f;
+                    G[j][2] += n.g[c][2] * f;
+                }
+            }
             const float v[3] = {coeff * pi[3 * p], coeff * pi[3 * p + 1], coeff * pi[3 * p + 2]};
 #pragma unroll
             for (int a = 0; a < 3; ++a) xi[3 * p + a] += v[0] * G[0][a] + v[1] * G[1][a] + v[2] * G[2][a];
@@ -422,17 +445,18 @@ k_unkick_vjp(const float* __restrict__ disp, float* __restrict__ mom, const floa
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_wgrad(const float* __restrict__ mesh, long pitch, float g_scale, float* __restrict__ disp,
-        const float* __restrict__ mom, float* __restrict__ xi, float* __restrict__ pi,
+k_wgrad(const float* __restrict__ mesh, long pitch, float g_scale, uint32_t* __restrict__ xq,
+        const int32_t* __restrict__ pq, float* __restrict__ xi, float* __restrict__ pi,
         const float* __restrict__ base, Lattice L, long P, float drift, int mode,
         double* __restrict__ partials) {
     Lattice Lm = L;
     Lm.rp = pitch;
     double acc = 0.0;
-    for (long p = (long)blockIdx.x * kBlock + threadIdx.x; p < P; p += (long)gridDim.x * kBlock) {
+    for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
+         p += (long)gridDim.x * kBlock) {
         int ii[3];
         float t[3];
-        locate(disp + 3 * p, p, Lm, ii, t);
+        locate(xq + 3 * p, Lm, ii, t);
         Node8 n;
         nodes8(ii, t, Lm, n);
         float g[3] = {0.f, 0.f, 0.f};
@@ -453,16 +477,45 @@ k_wgrad(const float* __restrict__ mesh, long pitch, float g_scale, float* __rest
         if (mode == 1) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const float pm = mom[3 * p + a];
-                acc += (double)x[a] * pm;
+                const int32_t m = pq[3 * p + a];
+                acc += (double)x[a] * ((double)m * L.mom_unit);
                 pi[3 * p + a] += drift * x[a];
-                disp[3 * p + a] -= drift * pm;
+                xq[3 * p + a] -= drift_units(drift, m, L);
             }
         }
     }
     if (mode == 1 && partials) {
         double s = block_sum(acc);
         if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_to_fixed(const float* __restrict__ disp, uint32_t* __restrict__ xq, Lattice L, long P) {
+    for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
+         p += (long)gridDim.x * kBlock) {
+        int jj[3];
+        lattice_index(p, L.np, jj);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            xq[3 * p + a] = (uint32_t)jj[a] * L.qstep +
+                            (uint32_t)__float2ll_rn(__fmul_rn(disp[3 * p + a], L.len_to_pos));
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_from_fixed(const uint32_t* __restrict__ xq, const int32_t* __restrict__ pq, Lattice L, long P,
+             float* __restrict__ disp, float* __restrict__ mom) {
+    for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
+         p += (long)gridDim.x * kBlock) {
+        int jj[3];
+        lattice_index(p, L.np, jj);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int32_t d = (int32_t)(xq[3 * p + a] - (uint32_t)jj[a] * L.qstep);
+            if (disp) disp[3 * p + a] = (float)d * L.pos_to_len;
+            if (mom) mom[3 * p + a] = (float)pq[3 * p + a] * L.mom_unit;
+        }
     }
 }
 
@@ -493,15 +546,16 @@ k_reduce(const double* __restrict__ partials, int n, double* __restrict__ sums, 
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_recon_err(const float* __restrict__ a, const float* __restrict__ b, long P, float inv_cell,
+k_recon_err(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b, Lattice L, long P,
             double* partials, unsigned* maxbits) {
     double acc = 0.0;
     float mx = 0.f;
-    for (long p = (long)blockIdx.x * kBlock + threadIdx.x; p < P; p += (long)gridDim.x * kBlock) {
+    for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
+         p += (long)gridDim.x * kBlock) {
         float d2 = 0.f;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const float d = (a[3 * p + k] - b[3 * p + k]) * inv_cell;
+            const float d = (float)(int32_t)(a[3 * p + k] - b[3 * p + k]) * L.frac;
             d2 += d * d;
         }
         acc += d2;
@@ -513,22 +567,77 @@ k_recon_err(const float* __restrict__ a, const float* __restrict__ b, long P, fl
     if ((threadIdx.x & 63) == 0) atomicMax(maxbits, __float_as_uint(mx));
 }
 
+// x = q + D0 s, p = G0 s in fixed point for lattice particle p.
+__device__ __forceinline__ void ic_fixed(const float s[3], const int jj[3], float D0, float G0,
+                                         const Lattice& L, uint32_t x[3], int32_t m[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        x[a] = (uint32_t)jj[a] * L.qstep +
+               (uint32_t)__float2ll_rn(__fmul_rn(__fmul_rn(D0, s[a]), L.len_to_pos));
+        m[a] = __float2int_rn(__fmul_rn(__fmul_rn(G0, s[a]), L.inv_mom_unit));
+    }
+}
+
 __global__ void __launch_bounds__(kBlock)
-k_ic_state(const float* __restrict__ sm, long sStride, int np, long rp, float D0, float G0,
-           float* __restrict__ disp, float* __restrict__ mom, float* __restrict__ s_out) {
-    const long P = (long)np * np * np;
-    for (long p = (long)blockIdx.x * kBlock + threadIdx.x; p < P; p += (long)gridDim.x * kBlock) {
+k_ic_state(const float* __restrict__ sm, long sStride, long rp, float D0, float G0, Lattice L,
+           long P, uint32_t* __restrict__ xq, int32_t* __restrict__ pq, float* __restrict__ s_out) {
+    for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
+         p += (long)gridDim.x * kBlock) {
         int jj[3];
-        lattice_index(p, np, jj);
-        const long o = ((long)jj[0] * np + jj[1]) * rp + jj[2];
+        lattice_index(p, L.np, jj);
+        const long o = ((long)jj[0] * L.np + jj[1]) * rp + jj[2];
+        float s[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) s[a] = sm[a * sStride + o];
+        uint32_t x[3];
+        int32_t m[3];
+        ic_fixed(s, jj, D0, G0, L, x, m);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const float s = sm[a * sStride + o];
-            if (disp) disp[3 * p + a] = D0 * s;
-            if (mom) mom[3 * p + a] = G0 * s;
-            if (s_out) s_out[3 * p + a] = s;
+            if (xq) xq[3 * p + a] = x[a];
+            if (pq) pq[3 * p + a] = m[a];
+            if (s_out) s_out[3 * p + a] = s[a];
         }
     }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_ic_check(const float* __restrict__ sm, long sStride, long rp, float D0, float G0, Lattice L,
+           long P, const uint32_t* __restrict__ xq, const int32_t* __restrict__ pq,
+           double* partials, unsigned* maxbits) {
+    double ax = 0.0, ap = 0.0, aref = 0.0;
+    float mx = 0.f;
+    for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
+         p += (long)gridDim.x * kBlock) {
+        int jj[3];
+        lattice_index(p, L.np, jj);
+        const long o = ((long)jj[0] * L.np + jj[1]) * rp + jj[2];
+        float s[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) s[a] = sm[a * sStride + o];
+        uint32_t x[3];
+        int32_t m[3];
+        ic_fixed(s, jj, D0, G0, L, x, m);
+        float d2 = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float d = (float)(int32_t)(xq[3 * p + a] - x[a]) * L.frac;
+            d2 += d * d;
+            const double dp = (double)pq[3 * p + a] - m[a];
+            ap += dp * dp;
+            aref += (double)m[a] * m[a];
+        }
+        ax += d2;
+        mx = fmaxf(mx, sqrtf(d2));
+    }
+    double s0 = block_sum(ax), s1 = block_sum(ap), s2 = block_sum(aref);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = s0;
+        partials[gridDim.x + blockIdx.x] = s1;
+        partials[2 * gridDim.x + blockIdx.x] = s2;
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_down(mx, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(maxbits, __float_as_uint(mx));
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -552,7 +661,8 @@ k_from_pitched(const float* __restrict__ src, float* __restrict__ dst, int n, lo
 __global__ void __launch_bounds__(kBlock)
 k_deinterleave(const float* __restrict__ v, float* __restrict__ dst, long dstStride, int np, long rp) {
     const long P = (long)np * np * np;
-    for (long p = (long)blockIdx.x * kBlock + threadIdx.x; p < P; p += (long)gridDim.x * kBlock) {
+    for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
+         p += (long)gridDim.x * kBlock) {
         const long o = (p / np) * rp + (p % np);
 #pragma unroll
         for (int a = 0; a < 3; ++a) dst[a * dstStride + o] = v[3 * p + a];
@@ -631,12 +741,12 @@ void launch_zero(void* p, size_t bytes, hipStream_t s) {
     hipLaunchKernelGGL(k_zero, dim3(grid_for(n)), dim3(kBlock), 0, s, (uint32_t*)p, n);
 }
 
-void launch_bin(const float* disp, const Lattice& L, Bins& b, hipStream_t s) {
+void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, hipStream_t s) {
     const long P = (long)L.np * L.np * L.np;
     const long nk = b.nkeys();
     launch_zero(b.counts, (nk + 1) * sizeof(uint32_t), s);
     hipLaunchKernelGGL(k_bin_count, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       disp, L, b.tile, b.nt, P, b.counts, b.keys, b.ranks);
+                       xq, L, b.tile, b.nt, P, b.counts, b.keys, b.ranks);
     const long n = nk + 1;
     const long nb = (n + kScanChunk - 1) / kScanChunk;
     hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(kScanThreads), 0, s, b.counts,
@@ -649,64 +759,75 @@ void launch_bin(const float* disp, const Lattice& L, Bins& b, hipStream_t s) {
 }
 
 template <bool VEC>
-static void scatter_dispatch(const float* disp, const float* v, float coeff, const Lattice& L,
+static void scatter_dispatch(const uint32_t* xq, const float* v, float coeff, const Lattice& L,
                              const Bins& b, float* out, long outStride, hipStream_t s) {
     const unsigned ntiles = (unsigned)b.nt * b.nt * b.nt;
     switch (b.tile) {
         case 4:
-            hipLaunchKernelGGL((k_scatter_tile<4, VEC>), dim3(ntiles), dim3(kBlock), 0, s, disp, v,
+            hipLaunchKernelGGL((k_scatter_tile<4, VEC>), dim3(ntiles), dim3(kBlock), 0, s, xq, v,
                                coeff, L, b.nt, b.offsets, b.perm, out, outStride);
             break;
         case 8:
-            hipLaunchKernelGGL((k_scatter_tile<8, VEC>), dim3(ntiles), dim3(kBlock), 0, s, disp, v,
+            hipLaunchKernelGGL((k_scatter_tile<8, VEC>), dim3(ntiles), dim3(kBlock), 0, s, xq, v,
                                coeff, L, b.nt, b.offsets, b.perm, out, outStride);
             break;
         default:
-            hipLaunchKernelGGL((k_scatter_tile<16, VEC>), dim3(ntiles), dim3(kBlock), 0, s, disp, v,
+            hipLaunchKernelGGL((k_scatter_tile<16, VEC>), dim3(ntiles), dim3(kBlock), 0, s, xq, v,
                                coeff, L, b.nt, b.offsets, b.perm, out, outStride);
             break;
     }
 }
 
-void launch_scatter_density(const float* disp, const Lattice& L, const Bins& b, float* mesh,
+void launch_scatter_density(const uint32_t* xq, const Lattice& L, const Bins& b, float* mesh,
                             hipStream_t s) {
-    scatter_dispatch<false>(disp, nullptr, 0.f, L, b, mesh, 0, s);
+    scatter_dispatch<false>(xq, nullptr, 0.f, L, b, mesh, 0, s);
 }
 
-void launch_scatter_vec(const float* disp, const float* v, float coeff, const Lattice& L,
+void launch_scatter_vec(const uint32_t* xq, const float* v, float coeff, const Lattice& L,
                         const Bins& b, float* out, long outStride, hipStream_t s) {
-    scatter_dispatch<true>(disp, v, coeff, L, b, out, outStride, s);
+    scatter_dispatch<true>(xq, v, coeff, L, b, out, outStride, s);
 }
 
-void launch_gather_kick_drift(float* disp, float* mom, const float* fmesh, long fStride,
+void launch_gather_kick_drift(uint32_t* xq, int32_t* pq, const float* fmesh, long fStride,
                               const Lattice& L, float kick, float drift, int do_drift,
-                              float* ck_disp, float* ck_mom, hipStream_t s) {
+                              uint32_t* ck_x, int32_t* ck_p, hipStream_t s) {
     const long P = (long)L.np * L.np * L.np;
-    hipLaunchKernelGGL(k_gather_kick_drift, dim3(grid_for(P)), dim3(kBlock), 0, s, disp, mom, fmesh,
-                       fStride, L, P, kick, drift, do_drift, ck_disp, ck_mom);
+    hipLaunchKernelGGL(k_gather_kick_drift, dim3(grid_for(P)), dim3(kBlock), 0, s, xq, pq, fmesh,
+                       fStride, L, P, kick, drift, do_drift, ck_x, ck_p);
 }
 
-void launch_gather_force(const float* disp, const float* fmesh, long fStride, const Lattice& L,
+void launch_gather_force(const uint32_t* xq, const float* fmesh, long fStride, const Lattice& L,
                          float* out, hipStream_t s) {
     const long P = (long)L.np * L.np * L.np;
-    hipLaunchKernelGGL(k_gather_force, dim3(grid_for(P)), dim3(kBlock), 0, s, disp, fmesh, fStride,
+    hipLaunchKernelGGL(k_gather_force, dim3(grid_for(P)), dim3(kBlock), 0, s, xq, fmesh, fStride,
                        L, P, out);
 }
 
-void launch_unkick_vjp(const float* disp, float* mom, const float* fmesh, long fStride,
+void launch_unkick_vjp(const uint32_t* xq, int32_t* pq, const float* fmesh, long fStride,
                        const Lattice& L, float coeff, const float* pi, float* xi,
-                       double* partials, int nblocks, int do_unkick, hipStream_t s) {
+                       double* partials, int nblocks, hipStream_t s) {
     const long P = (long)L.np * L.np * L.np;
-    hipLaunchKernelGGL(k_unkick_vjp, dim3(nblocks), dim3(kBlock), 0, s, disp, mom, fmesh, fStride,
-                       L, P, coeff, pi, xi, partials, do_unkick);
+    hipLaunchKernelGGL(k_unkick_vjp, dim3(nblocks), dim3(kBlock), 0, s, xq, pq, fmesh, fStride,
+                       L, P, coeff, pi, xi, partials);
 }
 
-void launch_wgrad(const float* mesh, long pitch, float g_scale, float* disp, const float* mom,
+void launch_wgrad(const float* mesh, long pitch, float g_scale, uint32_t* xq, const int32_t* pq,
                   float* xi, float* pi, const float* base, const Lattice& L, float drift,
                   int mode, double* partials, int nblocks, hipStream_t s) {
     const long P = (long)L.np * L.np * L.np;
-    hipLaunchKernelGGL(k_wgrad, dim3(nblocks), dim3(kBlock), 0, s, mesh, pitch, g_scale, disp, mom,
+    hipLaunchKernelGGL(k_wgrad, dim3(nblocks), dim3(kBlock), 0, s, mesh, pitch, g_scale, xq, pq,
                        xi, pi, base, L, P, drift, mode, partials);
+}
+
+void launch_to_fixed(const float* disp, uint32_t* xq, const Lattice& L, hipStream_t s) {
+    const long P = (long)L.np * L.np * L.np;
+    hipLaunchKernelGGL(k_to_fixed, dim3(grid_for(P)), dim3(kBlock), 0, s, disp, xq, L, P);
+}
+
+void launch_from_fixed(const uint32_t* xq, const int32_t* pq, const Lattice& L, float* disp,
+                       float* mom, hipStream_t s) {
+    const long P = (long)L.np * L.np * L.np;
+    hipLaunchKernelGGL(k_from_fixed, dim3(grid_for(P)), dim3(kBlock), 0, s, xq, pq, L, P, disp, mom);
 }
 
 void launch_dot3(const float* a, const float* b, long P, double* partials, int nblocks,
@@ -718,17 +839,25 @@ void launch_reduce(const double* partials, int nblocks, double* sums, int slot, 
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, partials, nblocks, sums, slot);
 }
 
-void launch_recon_err(const float* a, const float* b, long P, float inv_cell, double* partials,
+void launch_recon_err(const uint32_t* a, const uint32_t* b, const Lattice& L, double* partials,
                       int nblocks, unsigned* maxbits, hipStream_t s) {
-    hipLaunchKernelGGL(k_recon_err, dim3(nblocks), dim3(kBlock), 0, s, a, b, P, inv_cell, partials,
-                       maxbits);
+    const long P = (long)L.np * L.np * L.np;
+    hipLaunchKernelGGL(k_recon_err, dim3(nblocks), dim3(kBlock), 0, s, a, b, L, P, partials, maxbits);
 }
 
-void launch_ic_state(const float* smesh, long sStride, int np, long rp, float D0, float G0,
-                     float* disp, float* mom, float* s_out, hipStream_t s) {
-    const long P = (long)np * np * np;
-    hipLaunchKernelGGL(k_ic_state, dim3(grid_for(P)), dim3(kBlock), 0, s, smesh, sStride, np, rp, D0,
-                       G0, disp, mom, s_out);
+void launch_ic_state(const float* smesh, long sStride, long rp, float D0, float G0,
+                     const Lattice& L, uint32_t* xq, int32_t* pq, float* s_out, hipStream_t s) {
+    const long P = (long)L.np * L.np * L.np;
+    hipLaunchKernelGGL(k_ic_state, dim3(grid_for(P)), dim3(kBlock), 0, s, smesh, sStride, rp, D0,
+                       G0, L, P, xq, pq, s_out);
+}
+
+void launch_ic_check(const float* smesh, long sStride, long rp, float D0, float G0,
+                     const Lattice& L, const uint32_t* xq, const int32_t* pq, double* partials,
+                     int nblocks, unsigned* maxbits, hipStream_t s) {
+    const long P = (long)L.np * L.np * L.np;
+    hipLaunchKernelGGL(k_ic_check, dim3(nblocks), dim3(kBlock), 0, s, smesh, sStride, rp, D0, G0,
+                       L, P, xq, pq, partials, maxbits);
 }
 
 void launch_to_pitched(const float* src, float* dst, int n, long rp, float scale,

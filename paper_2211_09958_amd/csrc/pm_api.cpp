@@ -34,7 +34,7 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kNParam = 4417;
 constexpr int kExtraSlots = 16 + 2 * PM_MAX_CHECKPOINTS;
-constexpr int kPartials = 4096;
+constexpr int kPartials = 3 * 4096;
 
 thread_local std::string g_err;
 
@@ -155,7 +155,9 @@ struct pm_ctx {
     int np, ng, cs, cs_p;
     long P;
     float2* C[4];
-    float *disp, *mom, *xi, *pi, *fin_disp, *fin_mom, *s_ic, *tmpv, *noise, *ckpt;
+    uint32_t *xq, *fin_x, *ckpt;   // fixed-point positions (working, final, checkpoints)
+    int32_t *pq, *fin_p;           // fixed-point momenta
+    float *xi, *pi, *s_ic, *tmpv, *noise;
     float *radial_f, *radial_ic, *radial_ic_dom, *theta, *gtheta, *fbar, *mlp_scratch;
     float2* tw;
     double *partials, *sums, *pkbins;
@@ -264,8 +266,10 @@ int upload_tables(pm_ctx* ctx) {
         // d sqrt(P/V)/dOm = dP/dOm / (2 sqrt(P V))
         ricd[n2] = (float)(dpk[n2] / (2.0 * std::sqrt(pk[n2] * vcell)) * norm_p / n2);
     }
-    const double norm_f = c.box / (2.0 * kPi) / ((double)ng * ng * ng);
-    for (long n2 = 0; n2 < ntf; ++n2) rf[n2] = n2 == 0 ? 0.f : (float)(norm_f / n2);
+    // same FP32 expression as the filter path (f * fscale / n2 with f = 1), so a
+    // zero filter reproduces the plain force bit for bit
+    const float fscale = (float)(c.box / (2.0 * kPi) / std::pow((double)ng, 3.0));
+    for (long n2 = 0; n2 < ntf; ++n2) rf[n2] = n2 == 0 ? 0.f : (1.0f * fscale) / (float)n2;
     std::vector<float2> tw(ng);
     for (int m = 0; m < ng; ++m) {
         const double ang = -2.0 * kPi * m / ng;
@@ -293,14 +297,14 @@ const float* force_radial(pm_ctx* ctx, double a) {
 
 // PM force meshes of particles at q + disp: bins, delta -> C0 (x,y-transformed
 // spectrum left in C0), F~_j real meshes in C1..C3.
-void compute_force(pm_ctx* ctx, const float* disp, double a) {
+void compute_force(pm_ctx* ctx, const uint32_t* xq, double a) {
     hipStream_t s = ctx->stream;
     const int ng = ctx->ng, cs = ctx->cs;
     const long cst = ctx->plan.cplx_elems;
     const double r = mesh_r(ng), c = mesh_c(ng), P = (double)ctx->P;
-    { KTimer t(ctx, PM_K_BIN, 32 * P); launch_bin(disp, ctx->lat, ctx->bins, s); }
+    { KTimer t(ctx, PM_K_BIN, 32 * P); launch_bin(xq, ctx->lat, ctx->bins, s); }
     { KTimer t(ctx, PM_K_SCATTER, 16 * P + r);
-      launch_scatter_density(disp, ctx->lat, ctx->bins, ctx->creal(0), s); }
+      launch_scatter_density(xq, ctx->lat, ctx->bins, ctx->creal(0), s); }
     { KTimer t(ctx, PM_K_FFT_X, r + c); launch_fft_x_r2c(ctx->C[0], ng, cs, 1, cst, ctx->tw, ng, s); }
     { KTimer t(ctx, PM_K_FFT_STRIDED, 2 * c);
       launch_fft_axis(ctx->C[0], ng, cs, 1, -1, 1, cst, ctx->tw, ng, s); }
@@ -315,13 +319,13 @@ void compute_force(pm_ctx* ctx, const float* disp, double a) {
 
 // delta_bar (real, in C0) = transposed spectral operator applied to the CIC
 // scatter of coeff * v at the current bins; filter cotangent into gtheta.
-void vjp_mesh(pm_ctx* ctx, const float* disp, const float* v, float coeff, double a) {
+void vjp_mesh(pm_ctx* ctx, const uint32_t* xq, const float* v, float coeff, double a) {
     hipStream_t s = ctx->stream;
     const int ng = ctx->ng, cs = ctx->cs;
     const long cst = ctx->plan.cplx_elems;
     const double r = mesh_r(ng), c = mesh_c(ng), P = (double)ctx->P;
     { KTimer t(ctx, PM_K_SCATTER_VEC, 28 * P + 3 * r);
-      launch_scatter_vec(disp, v, coeff, ctx->lat, ctx->bins, ctx->creal(1), ctx->creal_stride(), s); }
+      launch_scatter_vec(xq, v, coeff, ctx->lat, ctx->bins, ctx->creal(1), ctx->creal_stride(), s); }
     { KTimer t(ctx, PM_K_FFT_X, 3 * (r + c)); launch_fft_x_r2c(ctx->C[1], ng, cs, 3, cst, ctx->tw, ng, s); }
     { KTimer t(ctx, PM_K_FFT_STRIDED, 6 * c);
       launch_fft_axis(ctx->C[1], ng, cs, 1, -1, 3, cst, ctx->tw, ng, s); }
@@ -344,21 +348,23 @@ void vjp_mesh(pm_ctx* ctx, const float* disp, const float* v, float coeff, doubl
     { KTimer t(ctx, PM_K_FFT_X, r + c); launch_fft_x_c2r(ctx->C[0], ng, cs, 1, cst, ctx->tw, ng, s); }
 }
 
-// Zel'dovich displacement (a = 1) of the stored noise with the radial table:
-// writes s_out [P][3] (and disp = D0 s, mom = G0 s when given).
-void ic_synthesis(pm_ctx* ctx, const float* radial, float* s_out, float* disp, float* mom) {
+// Zel'dovich displacement (a = 1) of the stored noise with the radial table;
+// leaves s_j as real meshes in C1..C3 (particle-grid geometry) and writes
+// s_out [P][3] and the fixed-point state x = q + D0 s, p = G0 s (each nullable).
+void ic_synthesis(pm_ctx* ctx, const float* radial, float* s_out, uint32_t* xq, int32_t* pq) {
     hipStream_t s = ctx->stream;
     const int np = ctx->np, cs = ctx->cs_p, ng = ctx->ng;
     const long cst = ctx->plan.cplx_elems;
     const long rp = 2L * cs;
+    KTimer t(ctx, PM_K_OTHER, 0);
     launch_to_pitched(ctx->noise, ctx->creal(0), np, rp, 1.f, s);
     launch_fft_x_r2c(ctx->C[0], np, cs, 1, cst, ctx->tw, ng, s);
     launch_fft_axis(ctx->C[0], np, cs, 1, -1, 1, cst, ctx->tw, ng, s);
     launch_grad_z(ctx->C[0], ctx->C[1], cst, np, cs, radial, ctx->tw, ng, s);
     launch_fft_axis(ctx->C[1], np, cs, 1, 1, 3, cst, ctx->tw, ng, s);
     launch_fft_x_c2r(ctx->C[1], np, cs, 3, cst, ctx->tw, ng, s);
-    launch_ic_state(ctx->creal(1), ctx->creal_stride(), np, rp, (float)ctx->sched.D0,
-                    (float)ctx->sched.G0, disp, mom, s_out, s);
+    launch_ic_state(ctx->creal(1), ctx->creal_stride(), rp, (float)ctx->sched.D0,
+                    (float)ctx->sched.G0, ctx->lat, xq, pq, s_out, s);
 }
 
 // dL/dnoise = transpose of the Zel'dovich synthesis applied to s_bar [P][3].
@@ -367,6 +373,7 @@ void ic_transpose(pm_ctx* ctx, const float* s_bar, float* g_noise) {
     const int np = ctx->np, cs = ctx->cs_p, ng = ctx->ng;
     const long cst = ctx->plan.cplx_elems;
     const long rp = 2L * cs;
+    KTimer t(ctx, PM_K_OTHER, 0);
     launch_deinterleave(s_bar, ctx->creal(1), ctx->creal_stride(), np, rp, s);
     launch_fft_x_r2c(ctx->C[1], np, cs, 3, cst, ctx->tw, ng, s);
     launch_fft_axis(ctx->C[1], np, cs, 1, -1, 3, cst, ctx->tw, ng, s);
@@ -476,16 +483,16 @@ int pm_init(const pm_config* cfg, const pm_cosmology* cosmo, void* workspace, si
     ctx->cs_p = p.cs_p;
     ctx->P = p.P;
     for (int k = 0; k < 4; ++k) ctx->C[k] = ctx->at<float2>(p.cplx) + k * p.cplx_elems;
-    ctx->disp = ctx->at<float>(p.disp);
-    ctx->mom = ctx->at<float>(p.mom);
+    ctx->xq = ctx->at<uint32_t>(p.disp);
+    ctx->pq = ctx->at<int32_t>(p.mom);
     ctx->xi = ctx->at<float>(p.xi);
     ctx->pi = ctx->at<float>(p.pi);
-    ctx->fin_disp = ctx->at<float>(p.fin_disp);
-    ctx->fin_mom = ctx->at<float>(p.fin_mom);
+    ctx->fin_x = ctx->at<uint32_t>(p.fin_disp);
+    ctx->fin_p = ctx->at<int32_t>(p.fin_mom);
     ctx->s_ic = ctx->at<float>(p.s_ic);
     ctx->tmpv = ctx->at<float>(p.tmpv);
     ctx->noise = ctx->at<float>(p.noise);
-    ctx->ckpt = ctx->at<float>(p.ckpt);
+    ctx->ckpt = ctx->at<uint32_t>(p.ckpt);
     ctx->radial_f = ctx->at<float>(p.radial_f);
     ctx->radial_ic = ctx->at<float>(p.radial_ic);
     ctx->radial_ic_dom = ctx->at<float>(p.radial_ic_dom);
@@ -498,7 +505,24 @@ int pm_init(const pm_config* cfg, const pm_cosmology* cosmo, void* workspace, si
     ctx->gtheta = ctx->at<float>(p.gtheta);
     ctx->fbar = ctx->at<float>(p.fbar);
     ctx->mlp_scratch = ctx->at<float>(p.mlp_scratch);
-    ctx->lat = Lattice{ctx->np, ctx->ng, ctx->ng / ctx->np, (float)(ctx->ng / cfg->box), 2L * p.cs};
+    {
+        Lattice& L = ctx->lat;
+        int lg = 0;
+        while ((1 << lg) < ctx->ng) ++lg;
+        L.np = ctx->np;
+        L.ng = ctx->ng;
+        L.ratio = ctx->ng / ctx->np;
+        L.inv_cell = (float)(ctx->ng / cfg->box);
+        L.rp = 2L * p.cs;
+        L.shift = 32 - lg;
+        L.half = 1u << (L.shift - 1);
+        L.qstep = (uint32_t)(4294967296.0 / ctx->np);
+        L.frac = (float)std::ldexp(1.0, -L.shift);
+        L.len_to_pos = (float)(4294967296.0 / cfg->box);
+        L.pos_to_len = (float)(cfg->box / 4294967296.0);
+        L.mom_unit = (float)(cfg->box / ctx->ng * std::ldexp(1.0, -22));
+        L.inv_mom_unit = (float)(1.0 / ((double)cfg->box / ctx->ng * std::ldexp(1.0, -22)));
+    }
     ctx->bins.tile = p.tile;
     ctx->bins.nt = p.nt;
     ctx->bins.counts = ctx->at<uint32_t>(p.counts);
@@ -566,31 +590,34 @@ int pm_forward(pm_ctx* ctx, const float* noise, float* disp_out, float* mom_out,
     const pm_config& c = ctx->cfg;
     const Schedule& sc = ctx->sched;
     const int N = c.n_steps;
-    const size_t vec = (size_t)ctx->P * 3 * sizeof(float);
+    const size_t vec = (size_t)ctx->P * 3 * sizeof(uint32_t);
     hipEventRecord(ctx->ev[0], s);
     PM_TRY(copy_d2d(ctx, ctx->noise, noise, (size_t)ctx->P * sizeof(float)));
-    ic_synthesis(ctx, ctx->radial_ic, ctx->s_ic, ctx->disp, ctx->mom);
+    ic_synthesis(ctx, ctx->radial_ic, ctx->s_ic, ctx->xq, ctx->pq);
     for (int n = 0; n <= N; ++n) {
-        compute_force(ctx, ctx->disp, sc.a[n]);
+        compute_force(ctx, ctx->xq, sc.a[n]);
         const double kick = (n > 0 ? sc.kick_b[n - 1] : 0.0) + (n < N ? sc.kick_a[n] : 0.0);
-        float *ckd = nullptr, *ckm = nullptr;
+        uint32_t* ckx = nullptr;
+        int32_t* ckp = nullptr;
         if (c.checkpoint_every > 0 && n > 0 && n < N && n % c.checkpoint_every == 0) {
             const int slot = n / c.checkpoint_every - 1;
-            ckd = ctx->ckpt + (size_t)slot * 6 * ctx->P;
-            ckm = ckd + 3 * ctx->P;
+            ckx = ctx->ckpt + (size_t)slot * 6 * ctx->P;
+            ckp = reinterpret_cast<int32_t*>(ckx + 3 * ctx->P);
         }
-        KTimer t(ctx, PM_K_GATHER, (ckd ? 72.0 : 48.0) * ctx->P + 3 * mesh_r(ctx->ng));
-        launch_gather_kick_drift(ctx->disp, ctx->mom, ctx->creal(1), ctx->creal_stride(), ctx->lat,
-                                 (float)kick, n < N ? (float)sc.drift[n] : 0.f, n < N, ckd, ckm, s);
+        KTimer t(ctx, PM_K_GATHER, (ckx ? 72.0 : 48.0) * ctx->P + 3 * mesh_r(ctx->ng));
+        launch_gather_kick_drift(ctx->xq, ctx->pq, ctx->creal(1), ctx->creal_stride(), ctx->lat,
+                                 (float)kick, n < N ? (float)sc.drift[n] : 0.f, n < N, ckx, ckp, s);
     }
-    PM_TRY(copy_d2d(ctx, ctx->fin_disp, ctx->disp, vec));
-    PM_TRY(copy_d2d(ctx, ctx->fin_mom, ctx->mom, vec));
-    PM_TRY(copy_d2d(ctx, disp_out, ctx->disp, vec));
-    PM_TRY(copy_d2d(ctx, mom_out, ctx->mom, vec));
-    if (dens) {
-        launch_bin(ctx->disp, ctx->lat, ctx->bins, s);
-        launch_scatter_density(ctx->disp, ctx->lat, ctx->bins, ctx->creal(0), s);
-        launch_from_pitched(ctx->creal(0), dens, ctx->ng, ctx->lat.rp, s);
+    PM_TRY(copy_d2d(ctx, ctx->fin_x, ctx->xq, vec));
+    PM_TRY(copy_d2d(ctx, ctx->fin_p, ctx->pq, vec));
+    {
+        KTimer t(ctx, PM_K_OTHER, 0);
+        launch_from_fixed(ctx->xq, ctx->pq, ctx->lat, disp_out, mom_out, s);
+        if (dens) {
+            launch_bin(ctx->xq, ctx->lat, ctx->bins, s);
+            launch_scatter_density(ctx->xq, ctx->lat, ctx->bins, ctx->creal(0), s);
+            launch_from_pitched(ctx->creal(0), dens, ctx->ng, ctx->lat.rp, s);
+        }
     }
     hipEventRecord(ctx->ev[1], s);
     PM_TRY(ctx->hip_check("pm_forward"));
@@ -615,9 +642,11 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
     const int xD0 = slotX, xG0 = slotX + 1, xSig = slotX + 2, xOm = slotX + 3,
               xIc = slotX + 4, xIcMom = slotX + 5, xIcMomRef = slotX + 6, xCk = slotX + 8;
     const float mass = ctx->mass();
+    const double bytes_unkick = 72.0 * P + 3 * mesh_r(ctx->ng);
+    const double bytes_wgrad = 84.0 * P + mesh_r(ctx->ng);
     hipEventRecord(ctx->ev[2], s);
-    PM_TRY(copy_d2d(ctx, ctx->disp, ctx->fin_disp, vec));
-    PM_TRY(copy_d2d(ctx, ctx->mom, ctx->fin_mom, vec));
+    PM_TRY(copy_d2d(ctx, ctx->xq, ctx->fin_x, vec));
+    PM_TRY(copy_d2d(ctx, ctx->pq, ctx->fin_p, vec));
     launch_zero(ctx->sums, (2 * (size_t)N + 2 + kExtraSlots) * sizeof(double), s);
     launch_zero(ctx->maxbits, kExtraSlots * sizeof(unsigned), s);
     if (c.filter) launch_zero(ctx->gtheta, kNParam * sizeof(float), s);
@@ -625,84 +654,88 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
     else launch_zero(ctx->pi, vec, s);
 
     // seed at x_N: xi = dL/dx_N (+ m grad w . dL/ddelta)
-    compute_force(ctx, ctx->disp, sc.a[N]);
-    if (g_dens)
-        launch_wgrad(g_dens, ctx->ng, mass, ctx->disp, ctx->mom, ctx->xi, ctx->pi, g_disp, ctx->lat,
+    compute_force(ctx, ctx->xq, sc.a[N]);
+    if (g_dens) {
+        KTimer t(ctx, PM_K_WGRAD, 36.0 * P + mesh_r(ctx->ng));
+        launch_wgrad(g_dens, ctx->ng, mass, ctx->xq, ctx->pq, ctx->xi, ctx->pi, g_disp, ctx->lat,
                      0.f, 0, nullptr, nb, s);
-    else if (g_disp)
+    } else if (g_disp) {
         PM_TRY(copy_d2d(ctx, ctx->xi, g_disp, vec));
-    else
+    } else {
         launch_zero(ctx->xi, vec, s);
-    const double bytes_unkick = 72.0 * P + 3 * mesh_r(ctx->ng);
-    const double bytes_wgrad = 84.0 * P + mesh_r(ctx->ng);
+    }
     {
         KTimer t(ctx, PM_K_UNKICK_VJP, bytes_unkick);
-        launch_unkick_vjp(ctx->disp, ctx->mom, ctx->creal(1), ctx->creal_stride(), ctx->lat,
-                          (float)sc.kick_b[N - 1], ctx->pi, ctx->xi, ctx->partials, nb, 1, s);
+        launch_unkick_vjp(ctx->xq, ctx->pq, ctx->creal(1), ctx->creal_stride(), ctx->lat,
+                          (float)sc.kick_b[N - 1], ctx->pi, ctx->xi, ctx->partials, nb, s);
     }
     launch_reduce(ctx->partials, nb, ctx->sums, slotS + N, s);
 
     int nck = 0;
     for (int n = N - 1; n >= 0; --n) {
-        // (ii) + (iii) at x_{n+1}
+        // (ii) + (iii) at x_{n+1}; then un-drift to x_n
         const double c1 = sc.kick_b[n] + (n + 1 < N ? sc.kick_a[n + 1] : 0.0);
-        vjp_mesh(ctx, ctx->disp, ctx->pi, (float)c1, sc.a[n + 1]);
+        vjp_mesh(ctx, ctx->xq, ctx->pi, (float)c1, sc.a[n + 1]);
         {
             KTimer t(ctx, PM_K_WGRAD, bytes_wgrad);
-            launch_wgrad(ctx->creal(0), ctx->lat.rp, mass, ctx->disp, ctx->mom, ctx->xi, ctx->pi,
+            launch_wgrad(ctx->creal(0), ctx->lat.rp, mass, ctx->xq, ctx->pq, ctx->xi, ctx->pi,
                          nullptr, ctx->lat, (float)sc.drift[n], 1, ctx->partials, nb, s);
         }
         launch_reduce(ctx->partials, nb, ctx->sums, slotD + n, s);
-        // checkpoint reset at (x_n, p_{n+1/2})
+        // checkpoint: compare the reconstructed (x_n, p_{n+1/2}) and reset to it
         if (c.checkpoint_every > 0 && n > 0 && n % c.checkpoint_every == 0) {
             const int slot = n / c.checkpoint_every - 1;
-            const float* ckd = ctx->ckpt + (size_t)slot * 6 * P;
-            launch_recon_err(ctx->disp, ckd, P, ctx->lat.inv_cell, ctx->partials, nb,
-                             ctx->maxbits + 2 + nck, s);
+            const uint32_t* ckx = ctx->ckpt + (size_t)slot * 6 * P;
+            launch_recon_err(ctx->xq, ckx, ctx->lat, ctx->partials, nb, ctx->maxbits + 2 + nck, s);
             launch_reduce(ctx->partials, nb, ctx->sums, xCk + nck, s);
-            PM_TRY(copy_d2d(ctx, ctx->disp, ckd, vec));
-            PM_TRY(copy_d2d(ctx, ctx->mom, ckd + 3 * P, vec));
+            PM_TRY(copy_d2d(ctx, ctx->xq, ckx, vec));
+            PM_TRY(copy_d2d(ctx, ctx->pq, ckx + 3 * P, vec));
             ++nck;
         }
         // recompute F(x_n); un-kick and (i) at x_n
-        compute_force(ctx, ctx->disp, sc.a[n]);
+        compute_force(ctx, ctx->xq, sc.a[n]);
         const double c0 = (n > 0 ? sc.kick_b[n - 1] : 0.0) + sc.kick_a[n];
         {
             KTimer t(ctx, PM_K_UNKICK_VJP, bytes_unkick);
-            launch_unkick_vjp(ctx->disp, ctx->mom, ctx->creal(1), ctx->creal_stride(), ctx->lat,
-                              (float)c0, ctx->pi, ctx->xi, ctx->partials, nb, 1, s);
+            launch_unkick_vjp(ctx->xq, ctx->pq, ctx->creal(1), ctx->creal_stride(), ctx->lat,
+                              (float)c0, ctx->pi, ctx->xi, ctx->partials, nb, s);
         }
         launch_reduce(ctx->partials, nb, ctx->sums, slotS + n, s);
     }
     // (ii) + (iii) at x_0
-    vjp_mesh(ctx, ctx->disp, ctx->pi, (float)sc.kick_a[0], sc.a[0]);
-    launch_wgrad(ctx->creal(0), ctx->lat.rp, mass, ctx->disp, ctx->mom, ctx->xi, ctx->pi, nullptr,
-                 ctx->lat, 0.f, 2, nullptr, nb, s);
+    vjp_mesh(ctx, ctx->xq, ctx->pi, (float)sc.kick_a[0], sc.a[0]);
+    {
+        KTimer t(ctx, PM_K_WGRAD, 36.0 * P + mesh_r(ctx->ng));
+        launch_wgrad(ctx->creal(0), ctx->lat.rp, mass, ctx->xq, ctx->pq, ctx->xi, ctx->pi, nullptr,
+                     ctx->lat, 0.f, 2, nullptr, nb, s);
+    }
 
-    // ICs: x_0 = q + D0 s, p_0 = G0 s
+    // ICs: x_0 = q + D0 s, p_0 = G0 s.  Reconstruction check against the ICs.
     ic_synthesis(ctx, ctx->radial_ic, ctx->s_ic, nullptr, nullptr);
-    launch_axpby(ctx->tmpv, ctx->s_ic, (float)sc.D0, nullptr, 0.f, 3 * P, s);
-    launch_recon_err(ctx->disp, ctx->tmpv, P, ctx->lat.inv_cell, ctx->partials, nb, ctx->maxbits, s);
-    launch_reduce(ctx->partials, nb, ctx->sums, xIc, s);
-    launch_axpby(ctx->tmpv, ctx->s_ic, (float)sc.G0, nullptr, 0.f, 3 * P, s);
-    launch_axpby(ctx->disp, ctx->mom, 1.f, ctx->tmpv, -1.f, 3 * P, s);   // p_0 error (disp reused)
-    launch_dot3(ctx->disp, ctx->disp, P, ctx->partials, nb, s);
-    launch_reduce(ctx->partials, nb, ctx->sums, xIcMom, s);
-    launch_dot3(ctx->tmpv, ctx->tmpv, P, ctx->partials, nb, s);
-    launch_reduce(ctx->partials, nb, ctx->sums, xIcMomRef, s);
-    launch_dot3(ctx->xi, ctx->s_ic, P, ctx->partials, nb, s);
-    launch_reduce(ctx->partials, nb, ctx->sums, xD0, s);
-    launch_dot3(ctx->pi, ctx->s_ic, P, ctx->partials, nb, s);
-    launch_reduce(ctx->partials, nb, ctx->sums, xG0, s);
-    // s_bar = D0 xi + G0 pi
-    launch_axpby(ctx->tmpv, ctx->xi, (float)sc.D0, ctx->pi, (float)sc.G0, 3 * P, s);
-    launch_dot3(ctx->tmpv, ctx->s_ic, P, ctx->partials, nb, s);
-    launch_reduce(ctx->partials, nb, ctx->sums, xSig, s);
+    {
+        KTimer t(ctx, PM_K_OTHER, 0);
+        launch_ic_check(ctx->creal(1), ctx->creal_stride(), 2L * ctx->cs_p, (float)sc.D0,
+                        (float)sc.G0, ctx->lat, ctx->xq, ctx->pq, ctx->partials, nb, ctx->maxbits, s);
+        launch_reduce(ctx->partials, nb, ctx->sums, xIc, s);
+        launch_reduce(ctx->partials + nb, nb, ctx->sums, xIcMom, s);
+        launch_reduce(ctx->partials + 2 * nb, nb, ctx->sums, xIcMomRef, s);
+        launch_dot3(ctx->xi, ctx->s_ic, P, ctx->partials, nb, s);
+        launch_reduce(ctx->partials, nb, ctx->sums, xD0, s);
+        launch_dot3(ctx->pi, ctx->s_ic, P, ctx->partials, nb, s);
+        launch_reduce(ctx->partials, nb, ctx->sums, xG0, s);
+        // s_bar = D0 xi + G0 pi
+        launch_axpby(ctx->tmpv, ctx->xi, (float)sc.D0, ctx->pi, (float)sc.G0, 3 * P, s);
+        launch_dot3(ctx->tmpv, ctx->s_ic, P, ctx->partials, nb, s);
+        launch_reduce(ctx->partials, nb, ctx->sums, xSig, s);
+    }
     ic_transpose(ctx, ctx->tmpv, g_noise);
     // Omega_m dependence of P(k): s' = synthesis with d radial / d Omega_m
     ic_synthesis(ctx, ctx->radial_ic_dom, ctx->xi, nullptr, nullptr);
-    launch_dot3(ctx->tmpv, ctx->xi, P, ctx->partials, nb, s);
-    launch_reduce(ctx->partials, nb, ctx->sums, xOm, s);
+    {
+        KTimer t(ctx, PM_K_OTHER, 0);
+        launch_dot3(ctx->tmpv, ctx->xi, P, ctx->partials, nb, s);
+        launch_reduce(ctx->partials, nb, ctx->sums, xOm, s);
+    }
     if (g_filter) PM_TRY(copy_d2d(ctx, g_filter, ctx->gtheta, kNParam * sizeof(float)));
     hipEventRecord(ctx->ev[3], s);
     PM_TRY(ctx->hip_check("pm_adjoint"));
@@ -791,8 +824,9 @@ int pm_power_spectrum(pm_ctx* ctx, const float* dens, int32_t n_bins, double* k_
 int pm_density(pm_ctx* ctx, const float* disp, float* dens) {
     PM_TRY(ctx_check(ctx));
     if (!disp || !dens) return ctx->fail(PM_EINVAL, "disp and dens are required");
-    launch_bin(disp, ctx->lat, ctx->bins, ctx->stream);
-    launch_scatter_density(disp, ctx->lat, ctx->bins, ctx->creal(0), ctx->stream);
+    launch_to_fixed(disp, ctx->xq, ctx->lat, ctx->stream);
+    launch_bin(ctx->xq, ctx->lat, ctx->bins, ctx->stream);
+    launch_scatter_density(ctx->xq, ctx->lat, ctx->bins, ctx->creal(0), ctx->stream);
     launch_from_pitched(ctx->creal(0), dens, ctx->ng, ctx->lat.rp, ctx->stream);
     return ctx->hip_check("pm_density");
 }
@@ -801,8 +835,9 @@ int pm_force(pm_ctx* ctx, const float* disp, double a, float* force) {
     PM_TRY(ctx_check(ctx));
     if (!disp || !force) return ctx->fail(PM_EINVAL, "disp and force are required");
     if (ctx->cfg.filter && !ctx->have_filter) return ctx->fail(PM_ESTATE, "pm_set_filter not called");
-    compute_force(ctx, disp, a);
-    launch_gather_force(disp, ctx->creal(1), ctx->creal_stride(), ctx->lat, force, ctx->stream);
+    launch_to_fixed(disp, ctx->xq, ctx->lat, ctx->stream);
+    compute_force(ctx, ctx->xq, a);
+    launch_gather_force(ctx->xq, ctx->creal(1), ctx->creal_stride(), ctx->lat, force, ctx->stream);
     return ctx->hip_check("pm_force");
 }
 
@@ -812,14 +847,15 @@ int pm_force_vjp(pm_ctx* ctx, const float* disp, double a, const float* v, float
     if (ctx->cfg.filter && !ctx->have_filter) return ctx->fail(PM_ESTATE, "pm_set_filter not called");
     hipStream_t s = ctx->stream;
     const int nb = particle_blocks(ctx->P);
-    compute_force(ctx, disp, a);
+    launch_to_fixed(disp, ctx->xq, ctx->lat, s);
+    compute_force(ctx, ctx->xq, a);
     launch_zero(xi, (size_t)ctx->P * 3 * sizeof(float), s);
-    launch_unkick_vjp(disp, nullptr, ctx->creal(1), ctx->creal_stride(), ctx->lat, 1.f, v, xi,
-                      nullptr, nb, 0, s);
+    launch_unkick_vjp(ctx->xq, nullptr, ctx->creal(1), ctx->creal_stride(), ctx->lat, 1.f, v, xi,
+                      nullptr, nb, s);
     if (ctx->cfg.filter) launch_zero(ctx->gtheta, kNParam * sizeof(float), s);
-    vjp_mesh(ctx, disp, v, 1.f, a);
-    launch_wgrad(ctx->creal(0), ctx->lat.rp, ctx->mass(), const_cast<float*>(disp), nullptr, xi,
-                 nullptr, nullptr, ctx->lat, 0.f, 2, nullptr, nb, s);
+    vjp_mesh(ctx, ctx->xq, v, 1.f, a);
+    launch_wgrad(ctx->creal(0), ctx->lat.rp, ctx->mass(), ctx->xq, nullptr, xi, nullptr, nullptr,
+                 ctx->lat, 0.f, 2, nullptr, nb, s);
     return ctx->hip_check("pm_force_vjp");
 }
 
