@@ -13,6 +13,7 @@
 // axis-0 pass: one load of the spectrum, one forward column FFT, then for each
 // j a multiply and inverse column FFT straight to the output buffer, so the
 // spectrum is read once and each gradient component written once.
+#include <cmath>
 #include <type_traits>
 
 #include "fft_engine.h"
@@ -25,10 +26,15 @@ namespace {
 // Lanes-per-transform and values-per-lane choices per transform length.
 template <int H>
 struct Cfg {
-    static constexpr int E = H <= 16 ? H : (H == 256 || H == 1024 ? 16 : 8);
+    static constexpr int E = fft_values_per_lane(H);
     static constexpr int T = H / E;
-    // columns per work-group for strided passes: 64 KiB LDS tile at most
-    static constexpr int W = H >= 1024 ? 8 : 16;
+    // columns per work-group for strided passes (8 columns = 64-byte row
+    // segments; XCD-aware numbering keeps both halves of a 128-byte line on
+    // the same L2)
+    static constexpr int W = H >= 512 ? 8 : 16;
+    // minimum waves per SIMD requested from the compiler (caps VGPRs so that
+    // two work-groups fit on a CU for the large transforms)
+    static constexpr int MINW = H >= 512 ? 4 : 1;
     static constexpr int ROWS = T >= 256 ? 1 : 256 / T;   // rows per work-group, last axis
 };
 
@@ -37,26 +43,27 @@ struct Cfg {
 template <int N>
 __global__ void __launch_bounds__(Cfg<N / 2>::T * Cfg<N / 2>::ROWS)
 k_fft_x_r2c(float2* __restrict__ buf, int cs, long nrows, long bufStride,
-            const float2* __restrict__ tw, int ntw) {
+            const float2* __restrict__ tw, int ntw,
+            const float2* __restrict__ st) {
     constexpr int H = N / 2, E = Cfg<H>::E, T = Cfg<H>::T, ROWS = Cfg<H>::ROWS;
-    constexpr int LS = H + 1;
+    constexpr int LS = lds_slots(H);
     __shared__ float2 lds[ROWS * LS];
     const int r = threadIdx.x / T, j = threadIdx.x % T;
     const long row = (long)xcd_block(blockIdx.x, gridDim.x) * ROWS + r;
     const bool valid = row < nrows;
     float2* rowp = buf + blockIdx.y * bufStride + (valid ? row : 0) * cs;
-    const int twH = ntw / H, twN = ntw / N;
+    const int twN = ntw / N;
     float2 v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = valid ? rowp[j + e * T] : make_float2(0.f, 0.f);
     float2* L = lds + r * LS;
-    fft_lds<H, E, -1>(v, L, 1, 0, j, tw, twH);
+    fft_lds<H, E, -1>(v, L, 1, 0, j, st);
     __syncthreads();
     if (!valid) return;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = j + e * T;
-        float2 zk = L[k], zc = cconj(L[(H - k) & (H - 1)]);
+        float2 zk = L[lpad(k)], zc = cconj(L[lpad((H - k) & (H - 1))]);
         float2 A = cadd(zk, zc), B = csub(zk, zc);
         float2 w = tw[k * twN];
         float2 iwB = cmul_i<1>(cmul(w, B));
@@ -72,45 +79,48 @@ k_fft_x_r2c(float2* __restrict__ buf, int cs, long nrows, long bufStride,
 template <int N>
 __global__ void __launch_bounds__(Cfg<N / 2>::T * Cfg<N / 2>::ROWS)
 k_fft_x_c2r(float2* __restrict__ buf, int cs, long nrows, long bufStride,
-            const float2* __restrict__ tw, int ntw) {
+            const float2* __restrict__ tw, int ntw,
+            const float2* __restrict__ st) {
     constexpr int H = N / 2, E = Cfg<H>::E, T = Cfg<H>::T, ROWS = Cfg<H>::ROWS;
-    constexpr int LS = H + 1;
+    constexpr int LS = lds_slots(H);
     __shared__ float2 lds[ROWS * LS];
     const int r = threadIdx.x / T, j = threadIdx.x % T;
     const long row = (long)xcd_block(blockIdx.x, gridDim.x) * ROWS + r;
     const bool valid = row < nrows;
     float2* rowp = buf + blockIdx.y * bufStride + (valid ? row : 0) * cs;
-    const int twH = ntw / H, twN = ntw / N;
+    const int twN = ntw / N;
     float2* L = lds + r * LS;
 #pragma unroll
-    for (int e = 0; e < E; ++e) L[j + e * T] = valid ? rowp[j + e * T] : make_float2(0.f, 0.f);
-    if (j == 0) L[H] = valid ? rowp[H] : make_float2(0.f, 0.f);
+    for (int e = 0; e < E; ++e)
+        L[lpad(j + e * T)] = valid ? rowp[j + e * T] : make_float2(0.f, 0.f);
+    if (j == 0) L[lpad(H)] = valid ? rowp[H] : make_float2(0.f, 0.f);
     __syncthreads();
     float2 v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = j + e * T;
-        float2 xk = L[k], xc = cconj(L[H - k]);
+        float2 xk = L[lpad(k)], xc = cconj(L[lpad(H - k)]);
         float2 A = cadd(xk, xc), B = cmulc(csub(xk, xc), tw[k * twN]);
         v[e] = cadd(A, cmul_i<1>(B));
     }
     __syncthreads();
-    fft_lds<H, E, 1>(v, L, 1, 0, j, tw, twH);
+    fft_lds<H, E, 1>(v, L, 1, 0, j, st);
     __syncthreads();
     if (!valid) return;
 #pragma unroll
-    for (int e = 0; e < E; ++e) rowp[j + e * T] = L[j + e * T];
+    for (int e = 0; e < E; ++e) rowp[j + e * T] = L[lpad(j + e * T)];
 }
 
 // ---------------------------------------------------------- strided axes
 
 // Tile t -> (a, cb): column base a*A + cb*W, element p at + p*S.
 template <int H, int DIR>
-__global__ void __launch_bounds__(Cfg<H>::T * Cfg<H>::W)
+__global__ void __launch_bounds__(Cfg<H>::T * Cfg<H>::W, Cfg<H>::MINW)
 k_fft_strided(float2* __restrict__ buf, long S, long A, int ncb, long bufStride,
-              const float2* __restrict__ tw, int ntw) {
+              const float2* __restrict__ tw, int ntw,
+            const float2* __restrict__ st) {
     constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::W;
-    __shared__ float2 lds[H * W];
+    __shared__ float2 lds[lds_slots(H) * W];
     const int c = threadIdx.x % W, j = threadIdx.x / W;
     const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
     const int a = tile / ncb, cb = tile % ncb;
@@ -118,21 +128,25 @@ k_fft_strided(float2* __restrict__ buf, long S, long A, int ncb, long bufStride,
     float2 v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = base[(j + e * T) * S];
-    fft_lds<H, E, DIR>(v, lds, W, c, j, tw, ntw / H);
+    fft_lds<H, E, DIR>(v, lds, W, c, j, st);
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) base[(j + e * T) * S] = lds[(j + e * T) * W + c];
+    for (int e = 0; e < E; ++e) base[(j + e * T) * S] = lds[lpad(j + e * T) * W + c];
 }
 
 __device__ __forceinline__ int signed_freq(int p, int n) { return p < n / 2 ? p : p - n; }
 
-// Axis-0 pass with the fused gradient multiply (see launch_grad_z).
+// Axis-0 pass with the fused gradient multiply (see launch_grad_z).  Along an
+// axis-0 column n1 and n2 are fixed, so F~_1 and F~_2 are i n1 and i n2 times
+// the same inverse transform of radial * delta; only F~_0 needs an inverse
+// transform of its own: three column FFTs per tile instead of four.
 template <int H>
 __global__ void __launch_bounds__(Cfg<H>::T * Cfg<H>::W)
 k_grad_z(const float2* __restrict__ src, float2* __restrict__ dst, long dstStride, int cs,
-         int ncb, const float* __restrict__ radial, const float2* __restrict__ tw, int ntw) {
+         int ncb, const float* __restrict__ radial, const float2* __restrict__ tw, int ntw,
+            const float2* __restrict__ st) {
     constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::W, n = H;
-    __shared__ float2 lds[H * W];
+    __shared__ float2 lds[lds_slots(H) * W];
     const int c = threadIdx.x % W, j = threadIdx.x / W;
     const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
     const int i1 = tile / ncb, cb = tile % ncb;
@@ -142,47 +156,63 @@ k_grad_z(const float2* __restrict__ src, float2* __restrict__ dst, long dstStrid
     float2 v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = src[col + (j + e * T) * S];
-    fft_lds<H, E, -1>(v, lds, W, c, j, tw, ntw / H);
+    fft_lds<H, E, -1>(v, lds, W, c, j, st);
     __syncthreads();
-    float2 d[E];
-    float rad[E];
-    int n0s[E];
     const int n1 = signed_freq(i1, n);
     const bool in_half = k2 <= n / 2;
+    // radial * delta (kept: the F~_0 multiplier is n0 times it)
+    float2 d[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int p = j + e * T;
-        d[e] = lds[p * W + c];
         const int n0 = signed_freq(p, n);
-        n0s[e] = n0;
-        rad[e] = in_half ? radial[n0 * n0 + n1 * n1 + k2 * k2] : 0.f;
+        const float rad = in_half ? radial[n0 * n0 + n1 * n1 + k2 * k2] : 0.f;
+        const float2 x = lds[lpad(p) * W + c];
+        d[e] = make_float2(rad * x.x, rad * x.y);
+        v[e] = d[e];
     }
-#pragma unroll
-    for (int comp = 0; comp < 3; ++comp) {
+    __syncthreads();
+    fft_lds<H, E, 1>(v, lds, W, c, j, st);
+    __syncthreads();
+    {
+        // i n_j g for j = 1, 2 (zero on the Nyquist plane of the axis)
+        const float f1 = n1 == -n / 2 ? 0.f : (float)n1;
+        const float f2 = k2 == n / 2 ? 0.f : (float)k2;
+        float2* o1 = dst + dstStride + col;
+        float2* o2 = dst + 2 * dstStride + col;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int nc = comp == 0 ? n0s[e] : (comp == 1 ? n1 : k2);
-            const bool nyq = comp == 0 ? (n0s[e] == -n / 2) : (comp == 1 ? (n1 == -n / 2) : (k2 == n / 2));
-            const float f = nyq ? 0.f : (float)nc * rad[e];
-            v[e] = make_float2(-d[e].y * f, d[e].x * f);
+            const float2 g = lds[lpad(j + e * T) * W + c];
+            o1[(j + e * T) * S] = make_float2(-g.y * f1, g.x * f1);
+            o2[(j + e * T) * S] = make_float2(-g.y * f2, g.x * f2);
         }
-        __syncthreads();
-        fft_lds<H, E, 1>(v, lds, W, c, j, tw, ntw / H);
-        __syncthreads();
-        float2* out = dst + comp * dstStride + col;
-#pragma unroll
-        for (int e = 0; e < E; ++e) out[(j + e * T) * S] = lds[(j + e * T) * W + c];
     }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int n0 = signed_freq(j + e * T, n);
+        const float f0 = n0 == -n / 2 ? 0.f : (float)n0;
+        v[e] = make_float2(-d[e].y * f0, d[e].x * f0);
+    }
+    __syncthreads();
+    fft_lds<H, E, 1>(v, lds, W, c, j, st);
+    __syncthreads();
+    float2* o0 = dst + col;
+#pragma unroll
+    for (int e = 0; e < E; ++e) o0[(j + e * T) * S] = lds[lpad(j + e * T) * W + c];
 }
 
 // Axis-0 pass of the transposed gradient operator (see launch_grad_adj_z).
+// Sum_j conj(i n_j R) G_j = -i R (n0 G_0 + n1 G_1 + n2 G_2); n1 and n2 are fixed
+// along the column, so n1 G_1 + n2 G_2 is combined before its forward FFT:
+// three column FFTs per tile (four with the filter cotangent).
 template <int H, bool FILT>
 __global__ void __launch_bounds__(Cfg<H>::T * Cfg<H>::W)
 k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
              const float2* dens, int cs, int ncb, const float* __restrict__ radial,
-             float* __restrict__ fbar, float fscale, const float2* __restrict__ tw, int ntw) {
+             float* __restrict__ fbar, float fscale, const float2* __restrict__ tw, int ntw,
+            const float2* __restrict__ st) {
     constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::W, n = H;
-    __shared__ float2 lds[H * W];
+    __shared__ float2 lds[lds_slots(H) * W];
     const int c = threadIdx.x % W, j = threadIdx.x / W;
     const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
     const int i1 = tile / ncb, cb = tile % ncb;
@@ -191,65 +221,75 @@ k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
     const long col = (long)i1 * cs + k2;
     const int n1 = signed_freq(i1, n);
     const bool in_half = k2 <= n / 2;
-    float2 v[E], acc[E], d[E];
-    float fs[E];
+    const float f1 = n1 == -n / 2 ? 0.f : (float)n1;
+    const float f2 = k2 == n / 2 ? 0.f : (float)k2;
+    float2 v[E], a[E];
+    // forward FFT of G_0, kept as n0 G_0 (zero on its Nyquist plane)
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = src[col + (j + e * T) * S];
+    fft_lds<H, E, -1>(v, lds, W, c, j, st);
+    __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        acc[e] = make_float2(0.f, 0.f);
-        fs[e] = 0.f;
+        const int n0 = signed_freq(j + e * T, n);
+        const float f0 = n0 == -n / 2 ? 0.f : (float)n0;
+        const float2 g = lds[lpad(j + e * T) * W + c];
+        a[e] = make_float2(f0 * g.x, f0 * g.y);
     }
-    if constexpr (FILT) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = dens[col + (j + e * T) * S];
-        fft_lds<H, E, -1>(v, lds, W, c, j, tw, ntw / H);
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < E; ++e) d[e] = lds[(j + e * T) * W + c];
-    }
-#pragma unroll
-    for (int comp = 0; comp < 3; ++comp) {
-        const float2* in = src + comp * srcStride + col;
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = in[(j + e * T) * S];
-        __syncthreads();
-        fft_lds<H, E, -1>(v, lds, W, c, j, tw, ntw / H);
-        __syncthreads();
+    // forward FFT of n1 G_1 + n2 G_2, added
+    {
+        const float2* g1 = src + srcStride + col;
+        const float2* g2 = src + 2 * srcStride + col;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int p = j + e * T;
-            const float2 g = lds[p * W + c];
-            const int n0 = signed_freq(p, n);
-            const int nsq = n0 * n0 + n1 * n1 + k2 * k2;
-            const int nc = comp == 0 ? n0 : (comp == 1 ? n1 : k2);
-            const bool nyq = comp == 0 ? (n0 == -n / 2) : (comp == 1 ? (n1 == -n / 2) : (k2 == n / 2));
-            const float f = (nyq || !in_half) ? 0.f : (float)nc * radial[nsq];
-            // conj(i f) g = -i f g
-            acc[e].x += g.y * f;
-            acc[e].y -= g.x * f;
-            if constexpr (FILT) {
-                const float f0 = (nyq || !in_half || nsq == 0) ? 0.f : (float)nc * fscale / (float)nsq;
-                // Re(conj(g) * i f0 d) = f0 * (g.x * (-d.y) + g.y * d.x)
-                fs[e] += f0 * (g.y * d[e].x - g.x * d[e].y);
-            }
+            const float2 x = g1[(j + e * T) * S], y = g2[(j + e * T) * S];
+            v[e] = make_float2(f1 * x.x + f2 * y.x, f1 * x.y + f2 * y.y);
         }
     }
+    __syncthreads();
+    fft_lds<H, E, -1>(v, lds, W, c, j, st);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const float2 g = lds[lpad(j + e * T) * W + c];
+        a[e].x += g.x;
+        a[e].y += g.y;
+    }
     if constexpr (FILT) {
+        // dL/df(|n|^2) += mult Re(conj(Sum_j n_j G_j) i fscale/|n|^2 dens_k)
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = dens[col + (j + e * T) * S];
+        __syncthreads();
+        fft_lds<H, E, -1>(v, lds, W, c, j, st);
+        __syncthreads();
         if (in_half) {
             const float mult = (k2 == 0 || k2 == n / 2) ? 1.f : 2.f;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const int n0 = signed_freq(j + e * T, n);
                 const int nsq = n0 * n0 + n1 * n1 + k2 * k2;
-                if (nsq > 0) atomicAdd(&fbar[nsq], mult * fs[e]);
+                if (nsq > 0) {
+                    const float2 dk = lds[lpad(j + e * T) * W + c];
+                    // Re(conj(a) * i dk) = a.y dk.x - a.x dk.y
+                    const float fs = fscale / (float)nsq * (a[e].y * dk.x - a[e].x * dk.y);
+                    atomicAdd(&fbar[nsq], mult * fs);
+                }
             }
         }
     }
+    // delta_bar_k = -i R (n0 G_0 + n1 G_1 + n2 G_2)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int n0 = signed_freq(j + e * T, n);
+        const float rad = in_half ? radial[n0 * n0 + n1 * n1 + k2 * k2] : 0.f;
+        v[e] = make_float2(rad * a[e].y, -rad * a[e].x);
+    }
     __syncthreads();
-    fft_lds<H, E, 1>(acc, lds, W, c, j, tw, ntw / H);
+    fft_lds<H, E, 1>(v, lds, W, c, j, st);
     __syncthreads();
     float2* out = dst + col;
 #pragma unroll
-    for (int e = 0; e < E; ++e) out[(j + e * T) * S] = lds[(j + e * T) * W + c];
+    for (int e = 0; e < E; ++e) out[(j + e * T) * S] = lds[lpad(j + e * T) * W + c];
 }
 
 // Calls f(std::integral_constant<int, n>) for the supported power-of-two sizes.
@@ -269,95 +309,111 @@ void size_switch(int n, F&& f) {
 }
 
 template <int N>
-void x_r2c(float2* buf, int cs, int nbuf, long bufStride, const float2* tw, int ntw,
+void x_r2c(float2* buf, int cs, int nbuf, long bufStride, const Twiddles& tw,
            hipStream_t s) {
     constexpr int ROWS = Cfg<N / 2>::ROWS, T = Cfg<N / 2>::T;
     long nrows = (long)N * N;
     dim3 grid((unsigned)((nrows + ROWS - 1) / ROWS), nbuf);
-    hipLaunchKernelGGL(k_fft_x_r2c<N>, grid, dim3(T * ROWS), 0, s, buf, cs, nrows, bufStride, tw, ntw);
+    hipLaunchKernelGGL(k_fft_x_r2c<N>, grid, dim3(T * ROWS), 0, s, buf, cs, nrows, bufStride, tw.w, tw.n, tw.stages);
 }
 
 template <int N>
-void x_c2r(float2* buf, int cs, int nbuf, long bufStride, const float2* tw, int ntw,
+void x_c2r(float2* buf, int cs, int nbuf, long bufStride, const Twiddles& tw,
            hipStream_t s) {
     constexpr int ROWS = Cfg<N / 2>::ROWS, T = Cfg<N / 2>::T;
     long nrows = (long)N * N;
     dim3 grid((unsigned)((nrows + ROWS - 1) / ROWS), nbuf);
-    hipLaunchKernelGGL(k_fft_x_c2r<N>, grid, dim3(T * ROWS), 0, s, buf, cs, nrows, bufStride, tw, ntw);
+    hipLaunchKernelGGL(k_fft_x_c2r<N>, grid, dim3(T * ROWS), 0, s, buf, cs, nrows, bufStride, tw.w, tw.n, tw.stages);
 }
 
 template <int N>
-void strided(float2* buf, int cs, int axis, int dir, int nbuf, long bufStride, const float2* tw,
-             int ntw, hipStream_t s) {
+void strided(float2* buf, int cs, int axis, int dir, int nbuf, long bufStride, const Twiddles& tw, hipStream_t s) {
     constexpr int W = Cfg<N>::W, T = Cfg<N>::T;
     int ncb = cs / W;
     long S = axis == 1 ? cs : (long)N * cs;
     long A = axis == 1 ? (long)N * cs : cs;
     dim3 grid(N * ncb, nbuf);
     if (dir < 0)
-        hipLaunchKernelGGL((k_fft_strided<N, -1>), grid, dim3(T * W), 0, s, buf, S, A, ncb, bufStride, tw, ntw);
+        hipLaunchKernelGGL((k_fft_strided<N, -1>), grid, dim3(T * W), 0, s, buf, S, A, ncb, bufStride, tw.w, tw.n, tw.stages);
     else
-        hipLaunchKernelGGL((k_fft_strided<N, 1>), grid, dim3(T * W), 0, s, buf, S, A, ncb, bufStride, tw, ntw);
+        hipLaunchKernelGGL((k_fft_strided<N, 1>), grid, dim3(T * W), 0, s, buf, S, A, ncb, bufStride, tw.w, tw.n, tw.stages);
 }
 
 }  // namespace
 
-void launch_fft_x_r2c(float2* buf, int n, int cs, int nbuf, long bufStride, const float2* tw,
-                      int ntw, hipStream_t s) {
-    size_switch(n, [&](auto nn) { x_r2c<decltype(nn)::value>(buf, cs, nbuf, bufStride, tw, ntw, s); });
+void launch_fft_x_r2c(float2* buf, int n, int cs, int nbuf, long bufStride, const Twiddles& tw, hipStream_t s) {
+    size_switch(n, [&](auto nn) { x_r2c<decltype(nn)::value>(buf, cs, nbuf, bufStride, tw, s); });
 }
 
-void launch_fft_x_c2r(float2* buf, int n, int cs, int nbuf, long bufStride, const float2* tw,
-                      int ntw, hipStream_t s) {
-    size_switch(n, [&](auto nn) { x_c2r<decltype(nn)::value>(buf, cs, nbuf, bufStride, tw, ntw, s); });
+void launch_fft_x_c2r(float2* buf, int n, int cs, int nbuf, long bufStride, const Twiddles& tw, hipStream_t s) {
+    size_switch(n, [&](auto nn) { x_c2r<decltype(nn)::value>(buf, cs, nbuf, bufStride, tw, s); });
 }
 
 void launch_fft_axis(float2* buf, int n, int cs, int axis, int dir, int nbuf, long bufStride,
-                     const float2* tw, int ntw, hipStream_t s) {
+                     const Twiddles& tw, hipStream_t s) {
     size_switch(n, [&](auto nn) {
-        strided<decltype(nn)::value>(buf, cs, axis, dir, nbuf, bufStride, tw, ntw, s);
+        strided<decltype(nn)::value>(buf, cs, axis, dir, nbuf, bufStride, tw, s);
     });
 }
 
 void launch_grad_z(const float2* src, float2* dst, long dstStride, int n, int cs,
-                   const float* radial, const float2* tw, int ntw, hipStream_t s) {
+                   const float* radial, const Twiddles& tw, hipStream_t s) {
     size_switch(n, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
         constexpr int W = Cfg<NN>::W, T = Cfg<NN>::T;
         int ncb = cs / W;
         hipLaunchKernelGGL(k_grad_z<NN>, dim3(NN * ncb), dim3(T * W), 0, s, src, dst,
-                           dstStride, cs, ncb, radial, tw, ntw);
+                           dstStride, cs, ncb, radial, tw.w, tw.n, tw.stages);
     });
 }
 
 void launch_grad_adj_z(const float2* src, long srcStride, float2* dst, const float2* dens,
                        int n, int cs, const float* radial, float* fbar, float fscale,
-                       const float2* tw, int ntw, hipStream_t s) {
+                       const Twiddles& tw, hipStream_t s) {
     size_switch(n, [&](auto nn) {
         constexpr int NN = decltype(nn)::value;
         constexpr int W = Cfg<NN>::W, T = Cfg<NN>::T;
         int ncb = cs / W;
         if (fbar)
             hipLaunchKernelGGL((k_grad_adj_z<NN, true>), dim3(NN * ncb), dim3(T * W), 0, s, src,
-                               srcStride, dst, dens, cs, ncb, radial, fbar, fscale, tw, ntw);
+                               srcStride, dst, dens, cs, ncb, radial, fbar, fscale, tw.w, tw.n,
+                               tw.stages);
         else
             hipLaunchKernelGGL((k_grad_adj_z<NN, false>), dim3(NN * ncb), dim3(T * W), 0, s, src,
-                               srcStride, dst, dens, cs, ncb, radial, fbar, fscale, tw, ntw);
+                               srcStride, dst, dens, cs, ncb, radial, fbar, fscale, tw.w, tw.n,
+                               tw.stages);
     });
 }
 
-void launch_fft3_r2c(float2* buf, int n, int cs, int nbuf, long bufStride, const float2* tw,
-                     int ntw, hipStream_t s) {
-    launch_fft_x_r2c(buf, n, cs, nbuf, bufStride, tw, ntw, s);
-    launch_fft_axis(buf, n, cs, 1, -1, nbuf, bufStride, tw, ntw, s);
-    launch_fft_axis(buf, n, cs, 0, -1, nbuf, bufStride, tw, ntw, s);
+void fill_stage_twiddles(float2* table) {
+    constexpr double kTwoPi = 6.283185307179586476925286766559;
+    for (int i = 0; i < kStageTableSize; ++i) table[i] = make_float2(0.f, 0.f);
+    for (int H = 2; H <= kMaxFft; H *= 2) {
+        const int E = fft_values_per_lane(H);
+        for (int Ns = 1; Ns < H;) {
+            const int R = E < H / Ns ? E : H / Ns;
+            if (Ns > 1)
+                for (int r = 1; r < R; ++r)
+                    for (int k = 0; k < Ns; ++k) {
+                        const double ang = -kTwoPi * r * k / ((double)Ns * R);
+                        table[H + (Ns - 1) + (r - 1) * Ns + k] =
+                            make_float2((float)std::cos(ang), (float)std::sin(ang));
+                    }
+            Ns *= R;
+        }
+    }
 }
 
-void launch_fft3_c2r(float2* buf, int n, int cs, int nbuf, long bufStride, const float2* tw,
-                     int ntw, hipStream_t s) {
-    launch_fft_axis(buf, n, cs, 0, 1, nbuf, bufStride, tw, ntw, s);
-    launch_fft_axis(buf, n, cs, 1, 1, nbuf, bufStride, tw, ntw, s);
-    launch_fft_x_c2r(buf, n, cs, nbuf, bufStride, tw, ntw, s);
+void launch_fft3_r2c(float2* buf, int n, int cs, int nbuf, long bufStride, const Twiddles& tw, hipStream_t s) {
+    launch_fft_x_r2c(buf, n, cs, nbuf, bufStride, tw, s);
+    launch_fft_axis(buf, n, cs, 1, -1, nbuf, bufStride, tw, s);
+    launch_fft_axis(buf, n, cs, 0, -1, nbuf, bufStride, tw, s);
+}
+
+void launch_fft3_c2r(float2* buf, int n, int cs, int nbuf, long bufStride, const Twiddles& tw, hipStream_t s) {
+    launch_fft_axis(buf, n, cs, 0, 1, nbuf, bufStride, tw, s);
+    launch_fft_axis(buf, n, cs, 1, 1, nbuf, bufStride, tw, s);
+    launch_fft_x_c2r(buf, n, cs, nbuf, bufStride, tw, s);
 }
 
 }  // namespace pmx

@@ -10,9 +10,14 @@
 //   x[b + r*H/R], multiplies by W_{Ns R}^{r (b mod Ns)}, takes an R-point DFT,
 //   and writes x'[(b - b mod Ns) R + b mod Ns + r Ns]   (Stockham autosort).
 // Between stages the values go through LDS; the last stage leaves the result
-// in natural order in LDS, element p at lds[p*PS + off].
+// in natural order in LDS, element p at lds[lpad(p)*PS + off].  lpad inserts
+// one empty slot after every 16 elements: the first stage writes lanes R
+// elements apart, which without the gap would put every lane of a wave on the
+// same few LDS banks.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include "fft_plan.h"
 
 namespace pmx {
 
@@ -130,11 +135,17 @@ __device__ __forceinline__ void dft(float2* v) {
     else static_assert(R == 2, "unsupported radix");
 }
 
-// One Stockham stage of span Ns, then the rest recursively.
-// tw[m * twStride] = exp(-2 pi i m / H) for 0 <= m < H.
+// LDS slot of transform element p (see above); an H-point transform needs
+// lds_slots(H) slots.
+__device__ __forceinline__ int lpad(int p) { return p + (p >> 4); }
+constexpr int lds_slots(int H) { return H + H / 16 + 1; }
+
+// One Stockham stage of span Ns, then the rest recursively.  `st` is the
+// stage twiddle table of this transform length (see fft_plan.h): lanes with
+// consecutive k read consecutive entries.
 template <int H, int E, int DIR, int Ns>
 __device__ __forceinline__ void fft_stage(float2 (&v)[E], float2* lds, int PS, int off, int j,
-                                          const float2* __restrict__ tw, int twStride) {
+                                          const float2* __restrict__ st) {
     constexpr int REM = H / Ns;
     constexpr int R = E < REM ? E : REM;
     constexpr int T = H / E;
@@ -149,31 +160,33 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[E], float2* lds, int PS, i
         if constexpr (Ns > 1) {
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                float2 w = tw[(r * k * (H / (Ns * R))) * twStride];
+                const float2 w = st[(Ns - 1) + (r - 1) * Ns + k];
                 u[r] = DIR < 0 ? cmul(u[r], w) : cmulc(u[r], w);
             }
         }
         dft<R, DIR>(u);
         const int base = (b - k) * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[(base + r * Ns) * PS + off] = u[r];
+        for (int r = 0; r < R; ++r) lds[lpad(base + r * Ns) * PS + off] = u[r];
     }
     if constexpr (Ns * R < H) {
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = lds[(j + e * T) * PS + off];
+        for (int e = 0; e < E; ++e) v[e] = lds[lpad(j + e * T) * PS + off];
         __syncthreads();
-        fft_stage<H, E, DIR, Ns * R>(v, lds, PS, off, j, tw, twStride);
+        fft_stage<H, E, DIR, Ns * R>(v, lds, PS, off, j, st);
     }
 }
 
 // Full H-point transform; caller synchronises before reading the LDS result
-// and must make sure no lane still reads `lds` when this is entered.
+// and must make sure no lane still reads `lds` when this is entered.  `stages`
+// is the combined stage-twiddle table (fft_plan.h).
 template <int H, int E, int DIR>
 __device__ __forceinline__ void fft_lds(float2 (&v)[E], float2* lds, int PS, int off, int j,
-                                        const float2* __restrict__ tw, int twStride) {
+                                        const float2* __restrict__ stages) {
     static_assert((H & (H - 1)) == 0 && (E & (E - 1)) == 0 && E <= H, "power-of-two sizes");
-    fft_stage<H, E, DIR, 1>(v, lds, PS, off, j, tw, twStride);
+    static_assert(E == fft_values_per_lane(H), "lane shape must match the twiddle tables");
+    fft_stage<H, E, DIR, 1>(v, lds, PS, off, j, stages + H);
 }
 
 }  // namespace pmx

@@ -13,23 +13,32 @@ namespace pmx {
 
 inline int complex_row_stride(int n) { return ((n / 2 + 1) + 15) / 16 * 16; }
 
+// Twiddle tables on the device: w[m] = exp(-2 pi i m / n) (real-split
+// post-twiddles of the last-axis passes) and the per-stage tables of
+// fft_plan.h (kStageTableSize entries).
+struct Twiddles {
+    const float2* w;
+    int n;
+    const float2* stages;
+};
+// Host: fill the per-stage twiddle table (kStageTableSize entries).
+void fill_stage_twiddles(float2* table);
+
 // ---------------------------------------------------------------- FFT
 // Real rows -> half spectra along the last axis, in place, for `nbuf` buffers
 // `bufStride` float2 apart.  Unnormalised exp(-i k x).
-void launch_fft_x_r2c(float2* buf, int n, int cs, int nbuf, long bufStride, const float2* tw,
-                      int ntw, hipStream_t s);
+void launch_fft_x_r2c(float2* buf, int n, int cs, int nbuf, long bufStride, const Twiddles& tw, hipStream_t s);
 // Inverse of the above without the 1/n factor (Hermitian rows assumed).
-void launch_fft_x_c2r(float2* buf, int n, int cs, int nbuf, long bufStride, const float2* tw,
-                      int ntw, hipStream_t s);
+void launch_fft_x_c2r(float2* buf, int n, int cs, int nbuf, long bufStride, const Twiddles& tw, hipStream_t s);
 // Complex transform along axis 0 or 1, in place; dir = -1 forward, +1 inverse.
 void launch_fft_axis(float2* buf, int n, int cs, int axis, int dir, int nbuf, long bufStride,
-                     const float2* tw, int ntw, hipStream_t s);
+                     const Twiddles& tw, hipStream_t s);
 // Fused axis-0 pass of the force: forward axis-0 FFT of src (already
 // transformed along axes 2 and 1), multiply by M_j = i n_j radial[|n|^2] for
 // j = 0, 1, 2 (zero on the Nyquist plane of axis j), inverse axis-0 FFT, store
 // to dst + j*dstStride.
 void launch_grad_z(const float2* src, float2* dst, long dstStride, int n, int cs,
-                   const float* radial, const float2* tw, int ntw, hipStream_t s);
+                   const float* radial, const Twiddles& tw, hipStream_t s);
 // Fused axis-0 pass of the transpose: dst = inverse-axis-0 of
 // Sum_j conj(M_j) forward-axis-0(src + j*srcStride).  dst may equal the
 // `dens` buffer.  When fbar != nullptr also accumulates
@@ -37,12 +46,10 @@ void launch_grad_z(const float2* src, float2* dst, long dstStride, int n, int cs
 // (mult = 1 on the k2 = 0, n/2 planes, else 2) using forward-axis-0(dens).
 void launch_grad_adj_z(const float2* src, long srcStride, float2* dst, const float2* dens,
                        int n, int cs, const float* radial, float* fbar, float fscale,
-                       const float2* tw, int ntw, hipStream_t s);
+                       const Twiddles& tw, hipStream_t s);
 // Full 3-D transforms built from the passes above.
-void launch_fft3_r2c(float2* buf, int n, int cs, int nbuf, long bufStride, const float2* tw,
-                     int ntw, hipStream_t s);
-void launch_fft3_c2r(float2* buf, int n, int cs, int nbuf, long bufStride, const float2* tw,
-                     int ntw, hipStream_t s);
+void launch_fft3_r2c(float2* buf, int n, int cs, int nbuf, long bufStride, const Twiddles& tw, hipStream_t s);
+void launch_fft3_c2r(float2* buf, int n, int cs, int nbuf, long bufStride, const Twiddles& tw, hipStream_t s);
 
 // ---------------------------------------------------------------- particles
 // Particle state is fixed point so that kick and drift are exactly invertible:
@@ -72,7 +79,6 @@ struct Bins {
     uint32_t* offsets;  // [nt^3 * 8 + 1]
     uint32_t* keys;     // [P]
     uint32_t* ranks;    // [P]
-    uint32_t* perm;     // [P]
     uint32_t* scan_tmp; // scan block sums
     long nkeys() const { return (long)nt * nt * nt * 8; }
 };
@@ -80,8 +86,24 @@ struct Bins {
 int choose_tile(int ng);
 long scan_tmp_elems(long nkeys);
 
-// Counting sort of particles by (tile of the CIC base cell, spill class).
-void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, hipStream_t s);
+// Per-particle arrays that move together when the particles are re-sorted.
+struct Records {
+    int n = 0;
+    const uint32_t* src[6];
+    uint32_t* dst[6];
+    int words[6];       // 32-bit words per particle
+    void add(const void* from, void* to, int w) {
+        src[n] = static_cast<const uint32_t*>(from);
+        dst[n] = static_cast<uint32_t*>(to);
+        words[n] = w;
+        ++n;
+    }
+};
+
+// Counting sort of particles by (tile of the CIC base cell, spill class): bin
+// offsets into b, and every record array copied from src to dst in sorted
+// order (bins are contiguous ranges of the sorted arrays).
+void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, const Records& rec, hipStream_t s);
 // Density delta = rho - 1 (particle mass (ng/np)^3) into a real mesh with pitch
 // L.rp; every cell written once (no pre-zeroing), deterministic.
 void launch_scatter_density(const uint32_t* xq, const Lattice& L, const Bins& b, float* mesh,
@@ -90,42 +112,56 @@ void launch_scatter_density(const uint32_t* xq, const Lattice& L, const Bins& b,
 void launch_scatter_vec(const uint32_t* xq, const float* v, float coeff, const Lattice& L,
                         const Bins& b, float* out, long outStride, hipStream_t s);
 
-// Forward gather-kick-drift: F = gather(force meshes), p += kick F, then
-// optional checkpoint copy of (x, p), then x += drift p (if do_drift).
-void launch_gather_kick_drift(uint32_t* xq, int32_t* pq, const float* fmesh, long fStride,
-                              const Lattice& L, float kick, float drift, int do_drift,
-                              uint32_t* ck_x, int32_t* ck_p, hipStream_t s);
-// Gather the force only: out[p][j] = Sum w F_j.
-void launch_gather_force(const uint32_t* xq, const float* fmesh, long fStride, const Lattice& L,
-                         float* out, hipStream_t s);
-// Reverse step part 1 at x: F = gather; p -= coeff F (exact inverse of the
-// forward kick); xi += Sum_j coeff pi_j grad w . F~_j; block partials of
-// Sum pi . F (FP64).  pq may be null (no un-kick), pi may be null.
+// Gathers: one work-group per tile of the current bins (particles must be
+// sorted by those bins); partials (nullable) get one FP64 value per tile.
+long gather_blocks(const Bins& b);
+// F = gather(force meshes), p += kick F, optional checkpoint copy of (x, p) in
+// lattice order (by id), then x += drift p (if do_drift).
+void launch_gather_kick_drift(uint32_t* xq, int32_t* pq, const uint32_t* id, const float* fmesh,
+                              long fStride, const Lattice& L, const Bins& b, float kick,
+                              float drift, int do_drift, uint32_t* ck_x, int32_t* ck_p,
+                              hipStream_t s);
+// out[id[p]][j] = Sum w F_j (lattice order).
+void launch_gather_force(const uint32_t* xq, const uint32_t* id, const float* fmesh, long fStride,
+                         const Lattice& L, const Bins& b, float* out, hipStream_t s);
+// Reverse step at x: F = gather; p -= coeff F (exact inverse of the forward
+// kick; pq nullable); xi += coeff Sum_j pi_j grad w . F~_j; partials Sum pi . F.
 void launch_unkick_vjp(const uint32_t* xq, int32_t* pq, const float* fmesh, long fStride,
-                       const Lattice& L, float coeff, const float* pi, float* xi,
-                       double* partials, int nblocks, hipStream_t s);
-// xi (+)= g_scale * Sum grad w . mesh (mesh pitch given); mode 0: xi = base + g
-// (base nullable); mode 1: xi += g, partial Sum xi . p, pi += drift xi,
-// x -= drift p (exact inverse of the forward drift); mode 2: xi += g.
+                       const Lattice& L, const Bins& b, float coeff, const float* pi, float* xi,
+                       double* partials, hipStream_t s);
+// xi += g_scale Sum grad w . mesh (mesh row pitch given).  mode 1 also does the
+// rest of a reverse step: partials Sum xi . p, pi += drift xi, x -= drift p
+// (exact inverse of the forward drift); mode 2 only updates xi.
 void launch_wgrad(const float* mesh, long pitch, float g_scale, uint32_t* xq, const int32_t* pq,
-                  float* xi, float* pi, const float* base, const Lattice& L, float drift,
-                  int mode, double* partials, int nblocks, hipStream_t s);
-// Displacements (float, Mpc/h) -> fixed-point positions q + s.
-void launch_to_fixed(const float* disp, uint32_t* xq, const Lattice& L, hipStream_t s);
-// Fixed-point state -> displacement (minimum image of x - q) and momentum.
-void launch_from_fixed(const uint32_t* xq, const int32_t* pq, const Lattice& L, float* disp,
-                       float* mom, hipStream_t s);
+                  float* xi, float* pi, const Lattice& L, const Bins& b, float drift, int mode,
+                  double* partials, hipStream_t s);
+// Displacements (float, Mpc/h, lattice order) -> fixed-point positions q + s
+// in lattice order, id = identity.
+void launch_to_fixed(const float* disp, uint32_t* xq, uint32_t* id, const Lattice& L,
+                     hipStream_t s);
+// Fixed-point state (any order) -> displacement (minimum image of x - q) and
+// momentum in lattice order (disp, mom, pq nullable).
+void launch_from_fixed(const uint32_t* xq, const int32_t* pq, const uint32_t* id,
+                       const Lattice& L, float* disp, float* mom, hipStream_t s);
+// [P][3] float records: mode 0 out[k] = in[id[k]], mode 1 out[id[k]] = in[k].
+void launch_permute_by_id(const float* in, const uint32_t* id, float* out, long P, int mode,
+                          hipStream_t s);
+// Fixed-point state (any order) scattered to lattice order by id.
+void launch_state_to_lattice(const uint32_t* xq, const int32_t* pq, const uint32_t* id, long P,
+                             uint32_t* xq_out, int32_t* pq_out, hipStream_t s);
+void launch_iota(uint32_t* id, long P, hipStream_t s);
 int particle_blocks(long P);
 
-// Dot products over [P][3] arrays into FP64 block partials.
+// Dot products over [P][3] arrays into FP64 block partials (b indexed through
+// id when given: Sum_k a[k] . b[id[k]]).
 void launch_dot3(const float* a, const float* b, long P, double* partials, int nblocks,
-                 hipStream_t s);
+                 hipStream_t s, const uint32_t* id = nullptr);
 // sums[slot] = Sum of partials[0..nblocks)
 void launch_reduce(const double* partials, int nblocks, double* sums, int slot, hipStream_t s);
 // Reconstruction error of fixed-point positions in cells: partials of
-// Sum |a-b|^2 (minimum image), *maxbits (as float bits) = max |a-b|.
-void launch_recon_err(const uint32_t* a, const uint32_t* b, const Lattice& L, double* partials,
-                      int nblocks, unsigned* maxbits, hipStream_t s);
+// Sum_k |a[k] - b[id[k]]|^2 (minimum image), *maxbits (as float bits) = max.
+void launch_recon_err(const uint32_t* a, const uint32_t* id, const uint32_t* b, const Lattice& L,
+                      double* partials, int nblocks, unsigned* maxbits, hipStream_t s);
 
 // Zel'dovich state from three real meshes s_j (pitch rp, on the particle
 // lattice): x = q + D0 s, p = G0 s in fixed point (xq, pq nullable), s_out
@@ -133,10 +169,11 @@ void launch_recon_err(const uint32_t* a, const uint32_t* b, const Lattice& L, do
 // xq/pq: block partials of Sum|dx|^2 (cells^2), Sum|dp|^2 and Sum|p|^2 at
 // partials[0, nblocks, 2 nblocks) and max |dx| (cells) into *maxbits.
 void launch_ic_state(const float* smesh, long sStride, long rp, float D0, float G0,
-                     const Lattice& L, uint32_t* xq, int32_t* pq, float* s_out, hipStream_t s);
+                     const Lattice& L, uint32_t* xq, int32_t* pq, uint32_t* id, float* s_out,
+                     hipStream_t s);
 void launch_ic_check(const float* smesh, long sStride, long rp, float D0, float G0,
-                     const Lattice& L, const uint32_t* xq, const int32_t* pq, double* partials,
-                     int nblocks, unsigned* maxbits, hipStream_t s);
+                     const Lattice& L, const uint32_t* xq, const int32_t* pq, const uint32_t* id,
+                     double* partials, int nblocks, unsigned* maxbits, hipStream_t s);
 // Compact [n]^3 <-> pitched rows.
 void launch_to_pitched(const float* src, float* dst, int n, long rp, float scale,
                        hipStream_t s);
@@ -147,6 +184,9 @@ void launch_deinterleave(const float* v, float* dst, long dstStride, int np, lon
 // out = a * x + b * y over n floats (y nullable -> out = a x)
 void launch_axpby(float* out, const float* x, float a, const float* y, float b, long n,
                   hipStream_t s);
+// out[id[k]] = a x[k] + b y[k] over [P][3] records (lattice-order output).
+void launch_axpby_scatter(float* out, const float* x, float a, const float* y, float b,
+                          const uint32_t* id, long P, hipStream_t s);
 
 // Loss L = n^-3 Sum (d - t)^2 partials, g = 2 (d - t) / n^3 (nullable).
 void launch_mse(const float* d, const float* t, float* g, long n3, double* partials,

@@ -44,6 +44,27 @@ __device__ __forceinline__ void lattice_index(long p, int np, int jj[3]) {
     jj[0] = (int)(q / np);
 }
 
+// Tiles are numbered in Morton (Z) order so that consecutive bins, and hence
+// the work-groups resident on one XCD at a time, cover a compact 3-D block of
+// the mesh.  Tiles per side is a power of two <= 256.
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+    v &= 0xffu;
+    v = (v | (v << 8)) & 0x0f00fu;
+    v = (v | (v << 4)) & 0xc30c3u;
+    v = (v | (v << 2)) & 0x249249u;
+    return v;
+}
+__device__ __forceinline__ uint32_t compact3(uint32_t v) {
+    v &= 0x249249u;
+    v = (v | (v >> 2)) & 0xc30c3u;
+    v = (v | (v >> 4)) & 0x0f00fu;
+    v = (v | (v >> 8)) & 0xffu;
+    return v;
+}
+__device__ __forceinline__ uint32_t morton3(uint32_t t0, uint32_t t1, uint32_t t2) {
+    return (spread3(t0) << 2) | (spread3(t1) << 1) | spread3(t2);
+}
+
 // Base node index and fractional offset per axis from fixed-point positions.
 __device__ __forceinline__ void locate(const uint32_t* __restrict__ x3, const Lattice& L, int ii[3],
                                        float t[3]) {
@@ -93,8 +114,7 @@ k_bin_count(const uint32_t* __restrict__ xq, Lattice L, int tile, int nt, long P
         int ii[3];
         float t[3];
         locate(xq + 3 * i, L, ii, t);
-        uint32_t tix = ((uint32_t)(ii[0] / tile) * nt + (uint32_t)(ii[1] / tile)) * nt +
-                       (uint32_t)(ii[2] / tile);
+        const uint32_t tix = morton3(ii[0] / tile, ii[1] / tile, ii[2] / tile);
         uint32_t cls = ((ii[0] % tile == tile - 1) << 2) | ((ii[1] % tile == tile - 1) << 1) |
                        (ii[2] % tile == tile - 1);
         key = tix * 8 + cls;
@@ -192,11 +212,27 @@ k_scan_add(uint32_t* __restrict__ out, long n, const uint32_t* __restrict__ bsum
         if (base + k < n) out[base + k] += add;
 }
 
+// Move every record of particle i to its sorted slot offsets[key] + rank.
 __global__ void __launch_bounds__(kBlock)
-k_bin_permute(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ ranks,
-              const uint32_t* __restrict__ offsets, long P, uint32_t* __restrict__ perm) {
+k_permute(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ ranks,
+          const uint32_t* __restrict__ offsets, long P, Records rec) {
     const long i = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (i < P) perm[offsets[keys[i]] + ranks[i]] = (uint32_t)i;
+    if (i >= P) return;
+    const long slot = offsets[keys[i]] + ranks[i];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+        if (a >= rec.n) break;
+        const int w = rec.words[a];
+        const uint32_t* src = rec.src[a] + i * w;
+        uint32_t* dst = rec.dst[a] + slot * w;
+        if (w == 3) {
+            dst[0] = src[0];
+            dst[1] = src[1];
+            dst[2] = src[2];
+        } else {
+            for (int k = 0; k < w; ++k) dst[k] = src[k];
+        }
+    }
 }
 
 // ------------------------------------------------------------- scatter
@@ -208,7 +244,7 @@ __device__ __forceinline__ void tile_range(int r, int tx, int ty, int tz, int nt
                                            const uint32_t* __restrict__ offsets,
                                            uint32_t* rs, uint32_t* re) {
     if (r == 0) {
-        const uint32_t k0 = (((uint32_t)tx * nt + ty) * nt + tz) * 8;
+        const uint32_t k0 = morton3(tx, ty, tz) * 8;
         *rs = offsets[k0];
         *re = offsets[k0 + 8];
         return;
@@ -221,7 +257,7 @@ __device__ __forceinline__ void tile_range(int r, int tx, int ty, int tz, int nt
                     const int nx = (tx - ((S >> 2) & 1) + nt) % nt;
                     const int ny = (ty - ((S >> 1) & 1) + nt) % nt;
                     const int nz = (tz - (S & 1) + nt) % nt;
-                    const uint32_t k = (((uint32_t)nx * nt + ny) * nt + nz) * 8 + cls;
+                    const uint32_t k = morton3(nx, ny, nz) * 8 + cls;
                     *rs = offsets[k];
                     *re = offsets[k + 1];
                     return;
@@ -235,25 +271,38 @@ constexpr int kRanges = 20;
 template <int T, bool VEC>
 __global__ void __launch_bounds__(kBlock)
 k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, float coeff,
-               Lattice L, int nt, const uint32_t* __restrict__ offsets,
-               const uint32_t* __restrict__ perm, float* __restrict__ out, long outStride) {
+               Lattice L, int nt, const uint32_t* __restrict__ offsets, float* __restrict__ out,
+               long outStride) {
     constexpr int T3 = T * T * T;
     constexpr int NACC = VEC ? 3 : 1;
     using Acc = typename std::conditional<VEC, float, unsigned long long>::type;
     __shared__ Acc acc[NACC * T3];
-    __shared__ uint32_t rs[kRanges], re[kRanges];
-    const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
-    const int tz = tile % nt, ty = (tile / nt) % nt, tx = tile / (nt * nt);
+    __shared__ uint32_t rs[kRanges], pre[kRanges + 1];
+    const uint32_t tile = xcd_block(blockIdx.x, gridDim.x);
+    const int tx = compact3(tile >> 2), ty = compact3(tile >> 1), tz = compact3(tile);
     const int lo[3] = {tx * T, ty * T, tz * T};
     for (int c = threadIdx.x; c < NACC * T3; c += kBlock) acc[c] = (Acc)0;
-    if (threadIdx.x < kRanges) tile_range(threadIdx.x, tx, ty, tz, nt, offsets, &rs[threadIdx.x], &re[threadIdx.x]);
+    if (threadIdx.x < kRanges) {
+        uint32_t b, e;
+        tile_range(threadIdx.x, tx, ty, tz, nt, offsets, &b, &e);
+        rs[threadIdx.x] = b;
+        pre[threadIdx.x + 1] = e - b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        pre[0] = 0;
+        for (int r = 0; r < kRanges; ++r) pre[r + 1] += pre[r];
+    }
     __syncthreads();
     const int mask = L.ng - 1;
     const float mass = (float)(L.ratio * L.ratio * L.ratio);
-    for (int r = 0; r < kRanges; ++r) {
-        const uint32_t e = re[r];
-        for (uint32_t idx = rs[r] + threadIdx.x; idx < e; idx += kBlock) {
-            const long p = perm[idx];
+    // one flat index space over the 20 ranges, so every lane has work
+    const uint32_t total = pre[kRanges];
+    for (uint32_t k = threadIdx.x; k < total; k += kBlock) {
+        int r = 0;
+        while (pre[r + 1] <= k) ++r;
+        const long p = rs[r] + (k - pre[r]);   // particles are stored in bin order
+        {
             int ii[3];
             float t[3];
             locate(xq + 3 * p, L, ii, t);
@@ -310,188 +359,145 @@ k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, 
 }
 
 // ------------------------------------------------------------- gathers
+//
+// Gathers run one work-group per tile, like the scatter: the (T+1)^3 mesh
+// values the tile's particles can touch are loaded into LDS with coalesced
+// rows, then the particles of the tile's bin (contiguous in the sorted
+// records) interpolate from LDS.  The interpolation uses explicitly rounded
+// operations in a fixed order, so the forward gather and the reverse-time
+// re-gather produce the same bits.
 
-struct Node8 {
-    long idx[8];
-    float w[8];
-    float g[8][3];
+enum GatherMode { kKickDrift = 0, kForce = 1, kUnkickVjp = 2, kWgrad = 3 };
+
+struct GatherArgs {
+    uint32_t* xq;
+    int32_t* pq;
+    const uint32_t* id;
+    const float* mesh;    // 3 meshes mStride apart (1 for kWgrad)
+    long mStride;
+    long pitch;           // real-row pitch of the meshes
+    float coeff;          // kick coefficient, or the mesh scale for kWgrad
+    float drift;
+    int flag;             // kKickDrift: drift?; kWgrad: 1 full reverse step, 2 xi only
+    uint32_t* ck_x;       // kKickDrift checkpoint, lattice order (nullable)
+    int32_t* ck_p;
+    float* out;           // kForce output, lattice order
+    const float* pi_in;   // kUnkickVjp
+    float* xi;            // kUnkickVjp, kWgrad
+    float* pi;            // kWgrad
+    double* partials;     // one per tile (nullable)
 };
 
-// Indices, weights and weight gradients (per axis, in 1/length) of the 8 nodes.
-__device__ __forceinline__ void nodes8(const int ii[3], const float t[3], const Lattice& L,
-                                       Node8& n) {
+template <int T, int MODE>
+__global__ void __launch_bounds__(kBlock)
+k_gather_tile(GatherArgs A, Lattice L, int nt, const uint32_t* __restrict__ offsets) {
+    constexpr int NM = MODE == kWgrad ? 1 : 3;
+    constexpr int TH = T + 1, TH3 = TH * TH * TH;
+    __shared__ float mf[NM * TH3];
+    const uint32_t tile = xcd_block(blockIdx.x, gridDim.x);
+    const int lo[3] = {(int)compact3(tile >> 2) * T, (int)compact3(tile >> 1) * T,
+                       (int)compact3(tile) * T};
+    const uint32_t pbeg = offsets[tile * 8], pend = offsets[tile * 8 + 8];
     const int mask = L.ng - 1;
-    const float ic = L.inv_cell;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int c0 = c >> 2, c1 = (c >> 1) & 1, c2 = c & 1;
-        const int n0 = (ii[0] + c0) & mask, n1 = (ii[1] + c1) & mask, n2 = (ii[2] + c2) & mask;
-        n.idx[c] = ((long)n0 * L.ng + n1) * L.rp + n2;
-        const float a0 = c0 ? t[0] : 1.f - t[0];
-        const float a1 = c1 ? t[1] : 1.f - t[1];
-        const float a2 = c2 ? t[2] : 1.f - t[2];
-        const float d0 = c0 ? ic : -ic, d1 = c1 ? ic : -ic, d2 = c2 ? ic : -ic;
-        n.w[c] = __fmul_rn(__fmul_rn(a0, a1), a2);
-        n.g[c][0] = d0 * a1 * a2;
-        n.g[c][1] = a0 * d1 * a2;
-        n.g[c][2] = a0 * a1 * d2;
-    }
-}
-
-// F_j = Sum_c w_c F~_j(node c), with explicitly rounded operations so that the
-// forward gather and the reverse-time re-gather agree bit for bit.
-__device__ __forceinline__ void gather3(const Node8& n, const float* __restrict__ fm, long fStride,
-                                        float F[3]) {
-    F[0] = F[1] = F[2] = 0.f;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        F[0] = __fmaf_rn(n.w[c], fm[n.idx[c]], F[0]);
-        F[1] = __fmaf_rn(n.w[c], fm[fStride + n.idx[c]], F[1]);
-        F[2] = __fmaf_rn(n.w[c], fm[2 * fStride + n.idx[c]], F[2]);
-    }
-}
-
-__global__ void __launch_bounds__(kBlock)
-k_gather_kick_drift(uint32_t* __restrict__ xq, int32_t* __restrict__ pq,
-                    const float* __restrict__ fm, long fStride, Lattice L, long P, float kick,
-                    float drift, int do_drift, uint32_t* __restrict__ ck_x,
-                    int32_t* __restrict__ ck_p) {
-    for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
-         p += (long)gridDim.x * kBlock) {
-        uint32_t x[3] = {xq[3 * p], xq[3 * p + 1], xq[3 * p + 2]};
-        int ii[3];
-        float t[3];
-        locate(x, L, ii, t);
-        Node8 n;
-        nodes8(ii, t, L, n);
-        float F[3];
-        gather3(n, fm, fStride, F);
-        int32_t m[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) m[a] = pq[3 * p + a] + kick_units(kick, F[a], L);
-        if (ck_x) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                ck_x[3 * p + a] = x[a];
-                ck_p[3 * p + a] = m[a];
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            pq[3 * p + a] = m[a];
-            if (do_drift) xq[3 * p + a] = x[a] + drift_units(drift, m[a], L);
-        }
-    }
-}
-
-__global__ void __launch_bounds__(kBlock)
-k_gather_force(const uint32_t* __restrict__ xq, const float* __restrict__ fm, long fStride,
-               Lattice L, long P, float* __restrict__ out) {
-    for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
-         p += (long)gridDim.x * kBlock) {
-        int ii[3];
-        float t[3];
-        locate(xq + 3 * p, L, ii, t);
-        Node8 n;
-        nodes8(ii, t, L, n);
-        float F[3];
-        gather3(n, fm, fStride, F);
-        out[3 * p] = F[0];
-        out[3 * p + 1] = F[1];
-        out[3 * p + 2] = F[2];
-    }
-}
-
-__global__ void __launch_bounds__(kBlock)
-k_unkick_vjp(const uint32_t* __restrict__ xq, int32_t* __restrict__ pq,
-             const float* __restrict__ fm, long fStride, Lattice L, long P, float coeff,
-             const float* __restrict__ pi, float* __restrict__ xi, double* __restrict__ partials) {
     double acc = 0.0;
-    for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
-         p += (long)gridDim.x * kBlock) {
-        int ii[3];
-        float t[3];
-        locate(xq + 3 * p, L, ii, t);
-        Node8 n;
-        nodes8(ii, t, L, n);
-        float F[3];
-        gather3(n, fm, fStride, F);
-        if (pq) {
+    if (pbeg < pend) {   // uniform across the work-group
+        for (int c = threadIdx.x; c < TH3; c += kBlock) {
+            const int l2 = c % TH, l1 = (c / TH) % TH, l0 = c / (TH * TH);
+            const long g = ((long)((lo[0] + l0) & mask) * L.ng + ((lo[1] + l1) & mask)) * A.pitch +
+                           ((lo[2] + l2) & mask);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) pq[3 * p + a] -= kick_units(coeff, F[a], L);
+            for (int m = 0; m < NM; ++m) mf[m * TH3 + c] = A.mesh[m * A.mStride + g];
         }
-        if (pi) {
-            float G[3][3] = {{0.f}};
+        __syncthreads();
+        const float ic = L.inv_cell;
+        for (uint32_t p = pbeg + threadIdx.x; p < pend; p += kBlock) {
+            uint32_t x[3] = {A.xq[3 * p], A.xq[3 * p + 1], A.xq[3 * p + 2]};
+            int ii[3];
+            float t[3];
+            locate(x, L, ii, t);
+            int b[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) b[a] = (ii[a] - lo[a]) & mask;   // in [0, T)
+            float F[NM] = {0.f}, G[NM][3] = {{0.f}};
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
+                const int c0 = c >> 2, c1 = (c >> 1) & 1, c2 = c & 1;
+                const int li = ((b[0] + c0) * TH + b[1] + c1) * TH + b[2] + c2;
+                const float a0 = c0 ? t[0] : 1.f - t[0];
+                const float a1 = c1 ? t[1] : 1.f - t[1];
+                const float a2 = c2 ? t[2] : 1.f - t[2];
+                const float w = __fmul_rn(__fmul_rn(a0, a1), a2);
+                const float d0 = c0 ? ic : -ic, d1 = c1 ? ic : -ic, d2 = c2 ? ic : -ic;
 #pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    const float f = fm[j * fStride + n.idx[c]];
-                    G[j][0] += n.g[c][0] * f;
-                    G[j][1] += n.g[c][1] * f;
-                    G[j][2] += n.g[c][2] * f;
+                for (int m = 0; m < NM; ++m) {
+                    const float f = mf[m * TH3 + li];
+                    if constexpr (MODE != kWgrad) F[m] = __fmaf_rn(w, f, F[m]);
+                    if constexpr (MODE == kUnkickVjp || MODE == kWgrad) {
+                        G[m][0] += d0 * a1 * a2 * f;
+                        G[m][1] += a0 * d1 * a2 * f;
+                        G[m][2] += a0 * a1 * d2 * f;
+                    }
                 }
             }
-            const float v[3] = {coeff * pi[3 * p], coeff * pi[3 * p + 1], coeff * pi[3 * p + 2]};
+            if constexpr (MODE == kKickDrift) {
+                int32_t m[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) xi[3 * p + a] += v[0] * G[0][a] + v[1] * G[1][a] + v[2] * G[2][a];
-            acc += (double)pi[3 * p] * F[0] + (double)pi[3 * p + 1] * F[1] + (double)pi[3 * p + 2] * F[2];
-        }
-    }
-    if (partials) {
-        double s = block_sum(acc);
-        if (threadIdx.x == 0) partials[blockIdx.x] = s;
-    }
-}
-
-__global__ void __launch_bounds__(kBlock)
-k_wgrad(const float* __restrict__ mesh, long pitch, float g_scale, uint32_t* __restrict__ xq,
-        const int32_t* __restrict__ pq, float* __restrict__ xi, float* __restrict__ pi,
-        const float* __restrict__ base, Lattice L, long P, float drift, int mode,
-        double* __restrict__ partials) {
-    Lattice Lm = L;
-    Lm.rp = pitch;
-    double acc = 0.0;
-    for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
-         p += (long)gridDim.x * kBlock) {
-        int ii[3];
-        float t[3];
-        locate(xq + 3 * p, Lm, ii, t);
-        Node8 n;
-        nodes8(ii, t, Lm, n);
-        float g[3] = {0.f, 0.f, 0.f};
+                for (int a = 0; a < 3; ++a) m[a] = A.pq[3 * p + a] + kick_units(A.coeff, F[a], L);
+                if (A.ck_x) {
+                    const long q = A.id[p];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const float f = mesh[n.idx[c]];
-            g[0] += n.g[c][0] * f;
-            g[1] += n.g[c][1] * f;
-            g[2] += n.g[c][2] * f;
-        }
-        float x[3];
+                    for (int a = 0; a < 3; ++a) {
+                        A.ck_x[3 * q + a] = x[a];
+                        A.ck_p[3 * q + a] = m[a];
+                    }
+                }
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const float prev = mode == 0 ? (base ? base[3 * p + a] : 0.f) : xi[3 * p + a];
-            x[a] = prev + g_scale * g[a];
-            xi[3 * p + a] = x[a];
-        }
-        if (mode == 1) {
+                for (int a = 0; a < 3; ++a) {
+                    A.pq[3 * p + a] = m[a];
+                    if (A.flag) A.xq[3 * p + a] = x[a] + drift_units(A.drift, m[a], L);
+                }
+            } else if constexpr (MODE == kForce) {
+                const long q = A.id[p];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int32_t m = pq[3 * p + a];
-                acc += (double)x[a] * ((double)m * L.mom_unit);
-                pi[3 * p + a] += drift * x[a];
-                xq[3 * p + a] -= drift_units(drift, m, L);
+                for (int a = 0; a < 3; ++a) A.out[3 * q + a] = F[a];
+            } else if constexpr (MODE == kUnkickVjp) {
+                if (A.pq) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) A.pq[3 * p + a] -= kick_units(A.coeff, F[a], L);
+                }
+                const float pv[3] = {A.pi_in[3 * p], A.pi_in[3 * p + 1], A.pi_in[3 * p + 2]};
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    A.xi[3 * p + a] += A.coeff * (pv[0] * G[0][a] + pv[1] * G[1][a] + pv[2] * G[2][a]);
+                acc += (double)pv[0] * F[0] + (double)pv[1] * F[1] + (double)pv[2] * F[2];
+            } else {   // kWgrad
+                float xv[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    xv[a] = A.xi[3 * p + a] + A.coeff * G[0][a];
+                    A.xi[3 * p + a] = xv[a];
+                }
+                if (A.flag == 1) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const int32_t m = A.pq[3 * p + a];
+                        acc += (double)xv[a] * ((double)m * L.mom_unit);
+                        A.pi[3 * p + a] += A.drift * xv[a];
+                        A.xq[3 * p + a] = x[a] - drift_units(A.drift, m, L);
+                    }
+                }
             }
         }
     }
-    if (mode == 1 && partials) {
-        double s = block_sum(acc);
-        if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    if (A.partials) {
+        const double s = block_sum(acc);
+        if (threadIdx.x == 0) A.partials[tile] = s;
     }
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_to_fixed(const float* __restrict__ disp, uint32_t* __restrict__ xq, Lattice L, long P) {
+k_to_fixed(const float* __restrict__ disp, uint32_t* __restrict__ xq, uint32_t* __restrict__ id,
+           Lattice L, long P) {
     for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
          p += (long)gridDim.x * kBlock) {
         int jj[3];
@@ -500,32 +506,73 @@ k_to_fixed(const float* __restrict__ disp, uint32_t* __restrict__ xq, Lattice L,
         for (int a = 0; a < 3; ++a)
             xq[3 * p + a] = (uint32_t)jj[a] * L.qstep +
                             (uint32_t)__float2ll_rn(__fmul_rn(disp[3 * p + a], L.len_to_pos));
+        id[p] = (uint32_t)p;
     }
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_from_fixed(const uint32_t* __restrict__ xq, const int32_t* __restrict__ pq, Lattice L, long P,
-             float* __restrict__ disp, float* __restrict__ mom) {
+k_from_fixed(const uint32_t* __restrict__ xq, const int32_t* __restrict__ pq,
+             const uint32_t* __restrict__ id, Lattice L, long P, float* __restrict__ disp,
+             float* __restrict__ mom) {
     for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
          p += (long)gridDim.x * kBlock) {
+        const long q = id[p];
         int jj[3];
-        lattice_index(p, L.np, jj);
+        lattice_index(q, L.np, jj);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const int32_t d = (int32_t)(xq[3 * p + a] - (uint32_t)jj[a] * L.qstep);
-            if (disp) disp[3 * p + a] = (float)d * L.pos_to_len;
-            if (mom) mom[3 * p + a] = (float)pq[3 * p + a] * L.mom_unit;
+            if (disp) disp[3 * q + a] = (float)d * L.pos_to_len;
+            if (mom) mom[3 * q + a] = (float)pq[3 * p + a] * L.mom_unit;
         }
     }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_permute_by_id(const float* __restrict__ in, const uint32_t* __restrict__ id,
+                float* __restrict__ out, long P, int mode) {
+    for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
+         p += (long)gridDim.x * kBlock) {
+        const long q = id[p];
+        const long src = mode == 0 ? q : p, dst = mode == 0 ? p : q;
+        out[3 * dst] = in[3 * src];
+        out[3 * dst + 1] = in[3 * src + 1];
+        out[3 * dst + 2] = in[3 * src + 2];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_state_to_lattice(const uint32_t* __restrict__ xq, const int32_t* __restrict__ pq,
+                   const uint32_t* __restrict__ id, long P, uint32_t* __restrict__ xo,
+                   int32_t* __restrict__ po) {
+    for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
+         p += (long)gridDim.x * kBlock) {
+        const long q = id[p];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            xo[3 * q + a] = xq[3 * p + a];
+            po[3 * q + a] = pq[3 * p + a];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_iota(uint32_t* __restrict__ id, long P) {
+    for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
+         p += (long)gridDim.x * kBlock)
+        id[p] = (uint32_t)p;
 }
 
 // ------------------------------------------------------------- small kernels
 
 __global__ void __launch_bounds__(kBlock)
-k_dot3(const float* __restrict__ a, const float* __restrict__ b, long n, double* partials) {
+k_dot3(const float* __restrict__ a, const float* __restrict__ b, long P, double* partials,
+       const uint32_t* __restrict__ id) {
     double acc = 0.0;
-    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock)
-        acc += (double)a[i] * b[i];
+    for (long p = (long)blockIdx.x * kBlock + threadIdx.x; p < P; p += (long)gridDim.x * kBlock) {
+        const long q = id ? (long)id[p] : p;
+        acc += (double)a[3 * p] * b[3 * q] + (double)a[3 * p + 1] * b[3 * q + 1] +
+               (double)a[3 * p + 2] * b[3 * q + 2];
+    }
     double s = block_sum(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
@@ -546,16 +593,18 @@ k_reduce(const double* __restrict__ partials, int n, double* __restrict__ sums, 
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_recon_err(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b, Lattice L, long P,
-            double* partials, unsigned* maxbits) {
+k_recon_err(const uint32_t* __restrict__ a, const uint32_t* __restrict__ id,
+            const uint32_t* __restrict__ b, Lattice L, long P, double* partials,
+            unsigned* maxbits) {
     double acc = 0.0;
     float mx = 0.f;
     for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
          p += (long)gridDim.x * kBlock) {
+        const long q = id[p];
         float d2 = 0.f;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const float d = (float)(int32_t)(a[3 * p + k] - b[3 * p + k]) * L.frac;
+            const float d = (float)(int32_t)(a[3 * p + k] - b[3 * q + k]) * L.frac;
             d2 += d * d;
         }
         acc += d2;
@@ -580,7 +629,8 @@ __device__ __forceinline__ void ic_fixed(const float s[3], const int jj[3], floa
 
 __global__ void __launch_bounds__(kBlock)
 k_ic_state(const float* __restrict__ sm, long sStride, long rp, float D0, float G0, Lattice L,
-           long P, uint32_t* __restrict__ xq, int32_t* __restrict__ pq, float* __restrict__ s_out) {
+           long P, uint32_t* __restrict__ xq, int32_t* __restrict__ pq, uint32_t* __restrict__ id,
+           float* __restrict__ s_out) {
     for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
          p += (long)gridDim.x * kBlock) {
         int jj[3];
@@ -598,19 +648,21 @@ k_ic_state(const float* __restrict__ sm, long sStride, long rp, float D0, float 
             if (pq) pq[3 * p + a] = m[a];
             if (s_out) s_out[3 * p + a] = s[a];
         }
+        if (id) id[p] = (uint32_t)p;
     }
 }
 
 __global__ void __launch_bounds__(kBlock)
 k_ic_check(const float* __restrict__ sm, long sStride, long rp, float D0, float G0, Lattice L,
            long P, const uint32_t* __restrict__ xq, const int32_t* __restrict__ pq,
-           double* partials, unsigned* maxbits) {
+           const uint32_t* __restrict__ id, double* partials, unsigned* maxbits) {
     double ax = 0.0, ap = 0.0, aref = 0.0;
     float mx = 0.f;
     for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
          p += (long)gridDim.x * kBlock) {
+        // the state is in sorted order: compare with the ICs of lattice particle id[p]
         int jj[3];
-        lattice_index(p, L.np, jj);
+        lattice_index(id[p], L.np, jj);
         const long o = ((long)jj[0] * L.np + jj[1]) * rp + jj[2];
         float s[3];
 #pragma unroll
@@ -677,6 +729,16 @@ k_axpby(float* __restrict__ out, const float* __restrict__ x, float a, const flo
 }
 
 __global__ void __launch_bounds__(kBlock)
+k_axpby_scatter(float* __restrict__ out, const float* __restrict__ x, float a,
+                const float* __restrict__ y, float b, const uint32_t* __restrict__ id, long P) {
+    for (long p = (long)blockIdx.x * kBlock + threadIdx.x; p < P; p += (long)gridDim.x * kBlock) {
+        const long q = id[p];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) out[3 * q + k] = a * x[3 * p + k] + b * y[3 * p + k];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
 k_mse(const float* __restrict__ d, const float* __restrict__ t, float* __restrict__ g, long n,
       float gscale, double* partials) {
     double acc = 0.0;
@@ -720,9 +782,11 @@ __global__ void __launch_bounds__(kBlock) k_zero(uint32_t* __restrict__ p, long 
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) p[i] = 0u;
 }
 
+// One thread per element: with XCD-aware numbering each XCD then sweeps one
+// contiguous window of the (bin-sorted) particles.
 int grid_for(long n) {
     long b = (n + kBlock - 1) / kBlock;
-    return (int)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
+    return (int)(b < 1 ? 1 : b);
 }
 
 }  // namespace
@@ -733,7 +797,7 @@ long scan_tmp_elems(long nkeys) { return (nkeys + 1 + kScanChunk - 1) / kScanChu
 
 int particle_blocks(long P) {
     long b = (P + kBlock - 1) / kBlock;
-    return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+    return (int)(b < 1 ? 1 : b);
 }
 
 void launch_zero(void* p, size_t bytes, hipStream_t s) {
@@ -741,7 +805,7 @@ void launch_zero(void* p, size_t bytes, hipStream_t s) {
     hipLaunchKernelGGL(k_zero, dim3(grid_for(n)), dim3(kBlock), 0, s, (uint32_t*)p, n);
 }
 
-void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, hipStream_t s) {
+void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, const Records& rec, hipStream_t s) {
     const long P = (long)L.np * L.np * L.np;
     const long nk = b.nkeys();
     launch_zero(b.counts, (nk + 1) * sizeof(uint32_t), s);
@@ -754,8 +818,8 @@ void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, hipStream_t s) {
     hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kScanThreads), 0, s, b.scan_tmp, nb);
     hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kScanThreads), 0, s, b.offsets, n,
                        b.scan_tmp);
-    hipLaunchKernelGGL(k_bin_permute, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       s, b.keys, b.ranks, b.offsets, P, b.perm);
+    hipLaunchKernelGGL(k_permute, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       b.keys, b.ranks, b.offsets, P, rec);
 }
 
 template <bool VEC>
@@ -765,15 +829,15 @@ static void scatter_dispatch(const uint32_t* xq, const float* v, float coeff, co
     switch (b.tile) {
         case 4:
             hipLaunchKernelGGL((k_scatter_tile<4, VEC>), dim3(ntiles), dim3(kBlock), 0, s, xq, v,
-                               coeff, L, b.nt, b.offsets, b.perm, out, outStride);
+                               coeff, L, b.nt, b.offsets, out, outStride);
             break;
         case 8:
             hipLaunchKernelGGL((k_scatter_tile<8, VEC>), dim3(ntiles), dim3(kBlock), 0, s, xq, v,
-                               coeff, L, b.nt, b.offsets, b.perm, out, outStride);
+                               coeff, L, b.nt, b.offsets, out, outStride);
             break;
         default:
             hipLaunchKernelGGL((k_scatter_tile<16, VEC>), dim3(ntiles), dim3(kBlock), 0, s, xq, v,
-                               coeff, L, b.nt, b.offsets, b.perm, out, outStride);
+                               coeff, L, b.nt, b.offsets, out, outStride);
             break;
     }
 }
@@ -788,76 +852,149 @@ void launch_scatter_vec(const uint32_t* xq, const float* v, float coeff, const L
     scatter_dispatch<true>(xq, v, coeff, L, b, out, outStride, s);
 }
 
-void launch_gather_kick_drift(uint32_t* xq, int32_t* pq, const float* fmesh, long fStride,
-                              const Lattice& L, float kick, float drift, int do_drift,
-                              uint32_t* ck_x, int32_t* ck_p, hipStream_t s) {
-    const long P = (long)L.np * L.np * L.np;
-    hipLaunchKernelGGL(k_gather_kick_drift, dim3(grid_for(P)), dim3(kBlock), 0, s, xq, pq, fmesh,
-                       fStride, L, P, kick, drift, do_drift, ck_x, ck_p);
+template <int MODE>
+static void gather_dispatch(const GatherArgs& A, const Lattice& L, const Bins& b, hipStream_t s) {
+    const unsigned ntiles = (unsigned)b.nt * b.nt * b.nt;
+    switch (b.tile) {
+        case 4:
+            hipLaunchKernelGGL((k_gather_tile<4, MODE>), dim3(ntiles), dim3(kBlock), 0, s, A, L, b.nt,
+                               b.offsets);
+            break;
+        case 8:
+            hipLaunchKernelGGL((k_gather_tile<8, MODE>), dim3(ntiles), dim3(kBlock), 0, s, A, L, b.nt,
+                               b.offsets);
+            break;
+        default:
+            hipLaunchKernelGGL((k_gather_tile<16, MODE>), dim3(ntiles), dim3(kBlock), 0, s, A, L,
+                               b.nt, b.offsets);
+            break;
+    }
 }
 
-void launch_gather_force(const uint32_t* xq, const float* fmesh, long fStride, const Lattice& L,
-                         float* out, hipStream_t s) {
-    const long P = (long)L.np * L.np * L.np;
-    hipLaunchKernelGGL(k_gather_force, dim3(grid_for(P)), dim3(kBlock), 0, s, xq, fmesh, fStride,
-                       L, P, out);
+long gather_blocks(const Bins& b) { return (long)b.nt * b.nt * b.nt; }
+
+void launch_gather_kick_drift(uint32_t* xq, int32_t* pq, const uint32_t* id, const float* fmesh,
+                              long fStride, const Lattice& L, const Bins& b, float kick,
+                              float drift, int do_drift, uint32_t* ck_x, int32_t* ck_p,
+                              hipStream_t s) {
+    GatherArgs A{};
+    A.xq = xq;
+    A.pq = pq;
+    A.id = id;
+    A.mesh = fmesh;
+    A.mStride = fStride;
+    A.pitch = L.rp;
+    A.coeff = kick;
+    A.drift = drift;
+    A.flag = do_drift;
+    A.ck_x = ck_x;
+    A.ck_p = ck_p;
+    gather_dispatch<kKickDrift>(A, L, b, s);
+}
+
+void launch_gather_force(const uint32_t* xq, const uint32_t* id, const float* fmesh, long fStride,
+                         const Lattice& L, const Bins& b, float* out, hipStream_t s) {
+    GatherArgs A{};
+    A.xq = const_cast<uint32_t*>(xq);
+    A.id = id;
+    A.mesh = fmesh;
+    A.mStride = fStride;
+    A.pitch = L.rp;
+    A.out = out;
+    gather_dispatch<kForce>(A, L, b, s);
 }
 
 void launch_unkick_vjp(const uint32_t* xq, int32_t* pq, const float* fmesh, long fStride,
-                       const Lattice& L, float coeff, const float* pi, float* xi,
-                       double* partials, int nblocks, hipStream_t s) {
-    const long P = (long)L.np * L.np * L.np;
-    hipLaunchKernelGGL(k_unkick_vjp, dim3(nblocks), dim3(kBlock), 0, s, xq, pq, fmesh, fStride,
-                       L, P, coeff, pi, xi, partials);
+                       const Lattice& L, const Bins& b, float coeff, const float* pi, float* xi,
+                       double* partials, hipStream_t s) {
+    GatherArgs A{};
+    A.xq = const_cast<uint32_t*>(xq);
+    A.pq = pq;
+    A.mesh = fmesh;
+    A.mStride = fStride;
+    A.pitch = L.rp;
+    A.coeff = coeff;
+    A.pi_in = pi;
+    A.xi = xi;
+    A.partials = partials;
+    gather_dispatch<kUnkickVjp>(A, L, b, s);
 }
 
 void launch_wgrad(const float* mesh, long pitch, float g_scale, uint32_t* xq, const int32_t* pq,
-                  float* xi, float* pi, const float* base, const Lattice& L, float drift,
-                  int mode, double* partials, int nblocks, hipStream_t s) {
-    const long P = (long)L.np * L.np * L.np;
-    hipLaunchKernelGGL(k_wgrad, dim3(nblocks), dim3(kBlock), 0, s, mesh, pitch, g_scale, xq, pq,
-                       xi, pi, base, L, P, drift, mode, partials);
+                  float* xi, float* pi, const Lattice& L, const Bins& b, float drift, int mode,
+                  double* partials, hipStream_t s) {
+    GatherArgs A{};
+    A.xq = xq;
+    A.pq = const_cast<int32_t*>(pq);
+    A.mesh = mesh;
+    A.pitch = pitch;
+    A.coeff = g_scale;
+    A.drift = drift;
+    A.flag = mode;
+    A.xi = xi;
+    A.pi = pi;
+    A.partials = partials;
+    gather_dispatch<kWgrad>(A, L, b, s);
 }
 
-void launch_to_fixed(const float* disp, uint32_t* xq, const Lattice& L, hipStream_t s) {
+void launch_to_fixed(const float* disp, uint32_t* xq, uint32_t* id, const Lattice& L,
+                     hipStream_t s) {
     const long P = (long)L.np * L.np * L.np;
-    hipLaunchKernelGGL(k_to_fixed, dim3(grid_for(P)), dim3(kBlock), 0, s, disp, xq, L, P);
+    hipLaunchKernelGGL(k_to_fixed, dim3(grid_for(P)), dim3(kBlock), 0, s, disp, xq, id, L, P);
 }
 
-void launch_from_fixed(const uint32_t* xq, const int32_t* pq, const Lattice& L, float* disp,
-                       float* mom, hipStream_t s) {
+void launch_from_fixed(const uint32_t* xq, const int32_t* pq, const uint32_t* id,
+                       const Lattice& L, float* disp, float* mom, hipStream_t s) {
     const long P = (long)L.np * L.np * L.np;
-    hipLaunchKernelGGL(k_from_fixed, dim3(grid_for(P)), dim3(kBlock), 0, s, xq, pq, L, P, disp, mom);
+    hipLaunchKernelGGL(k_from_fixed, dim3(grid_for(P)), dim3(kBlock), 0, s, xq, pq, id, L, P, disp,
+                       mom);
+}
+
+void launch_permute_by_id(const float* in, const uint32_t* id, float* out, long P, int mode,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_permute_by_id, dim3(grid_for(P)), dim3(kBlock), 0, s, in, id, out, P, mode);
+}
+
+void launch_state_to_lattice(const uint32_t* xq, const int32_t* pq, const uint32_t* id, long P,
+                             uint32_t* xq_out, int32_t* pq_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_state_to_lattice, dim3(grid_for(P)), dim3(kBlock), 0, s, xq, pq, id, P,
+                       xq_out, pq_out);
+}
+
+void launch_iota(uint32_t* id, long P, hipStream_t s) {
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(P)), dim3(kBlock), 0, s, id, P);
 }
 
 void launch_dot3(const float* a, const float* b, long P, double* partials, int nblocks,
-                 hipStream_t s) {
-    hipLaunchKernelGGL(k_dot3, dim3(nblocks), dim3(kBlock), 0, s, a, b, 3 * P, partials);
+                 hipStream_t s, const uint32_t* id) {
+    hipLaunchKernelGGL(k_dot3, dim3(nblocks), dim3(kBlock), 0, s, a, b, P, partials, id);
 }
 
 void launch_reduce(const double* partials, int nblocks, double* sums, int slot, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, partials, nblocks, sums, slot);
 }
 
-void launch_recon_err(const uint32_t* a, const uint32_t* b, const Lattice& L, double* partials,
-                      int nblocks, unsigned* maxbits, hipStream_t s) {
+void launch_recon_err(const uint32_t* a, const uint32_t* id, const uint32_t* b, const Lattice& L,
+                      double* partials, int nblocks, unsigned* maxbits, hipStream_t s) {
     const long P = (long)L.np * L.np * L.np;
-    hipLaunchKernelGGL(k_recon_err, dim3(nblocks), dim3(kBlock), 0, s, a, b, L, P, partials, maxbits);
+    hipLaunchKernelGGL(k_recon_err, dim3(nblocks), dim3(kBlock), 0, s, a, id, b, L, P, partials,
+                       maxbits);
 }
 
 void launch_ic_state(const float* smesh, long sStride, long rp, float D0, float G0,
-                     const Lattice& L, uint32_t* xq, int32_t* pq, float* s_out, hipStream_t s) {
+                     const Lattice& L, uint32_t* xq, int32_t* pq, uint32_t* id, float* s_out,
+                     hipStream_t s) {
     const long P = (long)L.np * L.np * L.np;
     hipLaunchKernelGGL(k_ic_state, dim3(grid_for(P)), dim3(kBlock), 0, s, smesh, sStride, rp, D0,
-                       G0, L, P, xq, pq, s_out);
+                       G0, L, P, xq, pq, id, s_out);
 }
 
 void launch_ic_check(const float* smesh, long sStride, long rp, float D0, float G0,
-                     const Lattice& L, const uint32_t* xq, const int32_t* pq, double* partials,
-                     int nblocks, unsigned* maxbits, hipStream_t s) {
+                     const Lattice& L, const uint32_t* xq, const int32_t* pq, const uint32_t* id,
+                     double* partials, int nblocks, unsigned* maxbits, hipStream_t s) {
     const long P = (long)L.np * L.np * L.np;
     hipLaunchKernelGGL(k_ic_check, dim3(nblocks), dim3(kBlock), 0, s, smesh, sStride, rp, D0, G0,
-                       L, P, xq, pq, partials, maxbits);
+                       L, P, xq, pq, id, partials, maxbits);
 }
 
 void launch_to_pitched(const float* src, float* dst, int n, long rp, float scale,
@@ -881,6 +1018,11 @@ void launch_deinterleave(const float* v, float* dst, long dstStride, int np, lon
 void launch_axpby(float* out, const float* x, float a, const float* y, float b, long n,
                   hipStream_t s) {
     hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(kBlock), 0, s, out, x, a, y, b, n);
+}
+
+void launch_axpby_scatter(float* out, const float* x, float a, const float* y, float b,
+                          const uint32_t* id, long P, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpby_scatter, dim3(grid_for(P)), dim3(kBlock), 0, s, out, x, a, y, b, id, P);
 }
 
 void launch_mse(const float* d, const float* t, float* g, long n3, double* partials,

@@ -18,11 +18,14 @@
 //   and Sum pi.F_n (= dL/dkick_a_n = dL/dkick_b_{n-1}).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <utility>
 #include <string>
 #include <vector>
 
+#include "fft_plan.h"
 #include "host_cosmo.h"
 #include "kernels.h"
 #include "pm.h"
@@ -34,7 +37,6 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kNParam = 4417;
 constexpr int kExtraSlots = 16 + 2 * PM_MAX_CHECKPOINTS;
-constexpr int kPartials = 3 * 4096;
 
 thread_local std::string g_err;
 
@@ -84,9 +86,10 @@ int n_checkpoints(const pm_config& c) {
 // Workspace plan: byte offsets of every buffer, 256-byte aligned.
 struct Plan {
     size_t total = 0;
-    size_t cplx, disp, mom, xi, pi, fin_disp, fin_mom, s_ic, tmpv, noise, ckpt;
-    size_t counts, offsets, keys, ranks, perm, scan_tmp;
-    size_t radial_f, radial_ic, radial_ic_dom, tw, partials, sums, maxbits, pkbins;
+    size_t cplx, disp, mom, xi, pi, disp2, mom2, xi2, pi2, id, id2, fin_disp, fin_mom, s_ic, tmpv,
+        noise, ckpt;
+    size_t counts, offsets, keys, ranks, scan_tmp;
+    size_t radial_f, radial_ic, radial_ic_dom, tw, tw_stages, partials, sums, maxbits, pkbins;
     size_t theta, gtheta, fbar, mlp_scratch;
     long cplx_elems, P, nkeys, ntab_f, ntab_p;
     int cs, cs_p, tile, nt, nckpt;
@@ -114,6 +117,12 @@ struct Plan {
         mom = take(vec);
         xi = take(vec);
         pi = take(vec);
+        disp2 = take(vec);
+        mom2 = take(vec);
+        xi2 = take(vec);
+        pi2 = take(vec);
+        id = take((size_t)P * sizeof(uint32_t));
+        id2 = take((size_t)P * sizeof(uint32_t));
         fin_disp = take(vec);
         fin_mom = take(vec);
         s_ic = take(vec);
@@ -124,13 +133,14 @@ struct Plan {
         offsets = take((nkeys + 1) * sizeof(uint32_t));
         keys = take((size_t)P * sizeof(uint32_t));
         ranks = take((size_t)P * sizeof(uint32_t));
-        perm = take((size_t)P * sizeof(uint32_t));
         scan_tmp = take(scan_tmp_elems(nkeys) * sizeof(uint32_t));
         radial_f = take(ntab_f * sizeof(float));
         radial_ic = take(ntab_p * sizeof(float));
         radial_ic_dom = take(ntab_p * sizeof(float));
         tw = take((size_t)ng * sizeof(float2));
-        partials = take(kPartials * sizeof(double));
+        tw_stages = take(kStageTableSize * sizeof(float2));
+        // FP64 block partials: one per 256-particle block, three sets for the IC check
+        partials = take((3 * (size_t)((P + 255) / 256) + 3 * 4096) * sizeof(double));
         sums = take((2 * (size_t)c.n_steps + 2 + kExtraSlots) * sizeof(double));
         maxbits = take(kExtraSlots * sizeof(unsigned));
         pkbins = take(3 * (size_t)ng * sizeof(double));
@@ -155,11 +165,19 @@ struct pm_ctx {
     int np, ng, cs, cs_p;
     long P;
     float2* C[4];
-    uint32_t *xq, *fin_x, *ckpt;   // fixed-point positions (working, final, checkpoints)
-    int32_t *pq, *fin_p;           // fixed-point momenta
-    float *xi, *pi, *s_ic, *tmpv, *noise;
+    // Working particle records, kept in bin order and double-buffered: each
+    // sort moves them from the current arrays to the *_alt arrays, which then
+    // become current.  id is the lattice index of each record.
+    uint32_t *xq, *xq_alt, *id, *id_alt;
+    int32_t *pq, *pq_alt;
+    float *xi, *xi_alt, *pi, *pi_alt;
+    uint32_t *fin_x, *ckpt;        // final state and checkpoints, lattice order
+    int32_t* fin_p;
+    float *s_ic, *tmpv, *noise;
     float *radial_f, *radial_ic, *radial_ic_dom, *theta, *gtheta, *fbar, *mlp_scratch;
     float2* tw;
+    float2* tw_stages;
+    Twiddles twd;
     double *partials, *sums, *pkbins;
     unsigned* maxbits;
     Schedule sched, dsched;
@@ -270,7 +288,8 @@ int upload_tables(pm_ctx* ctx) {
     // zero filter reproduces the plain force bit for bit
     const float fscale = (float)(c.box / (2.0 * kPi) / std::pow((double)ng, 3.0));
     for (long n2 = 0; n2 < ntf; ++n2) rf[n2] = n2 == 0 ? 0.f : (1.0f * fscale) / (float)n2;
-    std::vector<float2> tw(ng);
+    std::vector<float2> tw(ng), stages(kStageTableSize);
+    fill_stage_twiddles(stages.data());
     for (int m = 0; m < ng; ++m) {
         const double ang = -2.0 * kPi * m / ng;
         tw[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
@@ -280,6 +299,8 @@ int upload_tables(pm_ctx* ctx) {
         hipMemcpyAsync(ctx->radial_ic_dom, ricd.data(), ntp * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(ctx->radial_f, rf.data(), ntf * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(ctx->tw, tw.data(), ng * sizeof(float2), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(ctx->tw_stages, stages.data(), kStageTableSize * sizeof(float2),
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return ctx->fail(PM_EHIP, "uploading tables failed");
     return PM_OK;
@@ -295,26 +316,47 @@ const float* force_radial(pm_ctx* ctx, double a) {
     return ctx->radial_f;
 }
 
-// PM force meshes of particles at q + disp: bins, delta -> C0 (x,y-transformed
-// spectrum left in C0), F~_j real meshes in C1..C3.
-void compute_force(pm_ctx* ctx, const uint32_t* xq, double a) {
+// Sort the working records by bin (positions, momenta, ids, and with
+// `cotangents` also xi and pi), leaving the bin offsets in ctx->bins.
+void sort_particles(pm_ctx* ctx, bool cotangents) {
+    Records rec;
+    rec.add(ctx->xq, ctx->xq_alt, 3);
+    rec.add(ctx->pq, ctx->pq_alt, 3);
+    rec.add(ctx->id, ctx->id_alt, 1);
+    if (cotangents) {
+        rec.add(ctx->xi, ctx->xi_alt, 3);
+        rec.add(ctx->pi, ctx->pi_alt, 3);
+    }
+    launch_bin(ctx->xq, ctx->lat, ctx->bins, rec, ctx->stream);
+    std::swap(ctx->xq, ctx->xq_alt);
+    std::swap(ctx->pq, ctx->pq_alt);
+    std::swap(ctx->id, ctx->id_alt);
+    if (cotangents) {
+        std::swap(ctx->xi, ctx->xi_alt);
+        std::swap(ctx->pi, ctx->pi_alt);
+    }
+}
+
+// PM force meshes of the working particles: sort into bins, delta -> C0
+// (x,y-transformed spectrum left in C0), F~_j real meshes in C1..C3.
+void compute_force(pm_ctx* ctx, double a, bool cotangents) {
     hipStream_t s = ctx->stream;
     const int ng = ctx->ng, cs = ctx->cs;
     const long cst = ctx->plan.cplx_elems;
     const double r = mesh_r(ng), c = mesh_c(ng), P = (double)ctx->P;
-    { KTimer t(ctx, PM_K_BIN, 32 * P); launch_bin(xq, ctx->lat, ctx->bins, s); }
-    { KTimer t(ctx, PM_K_SCATTER, 16 * P + r);
-      launch_scatter_density(xq, ctx->lat, ctx->bins, ctx->creal(0), s); }
-    { KTimer t(ctx, PM_K_FFT_X, r + c); launch_fft_x_r2c(ctx->C[0], ng, cs, 1, cst, ctx->tw, ng, s); }
+    { KTimer t(ctx, PM_K_BIN, (cotangents ? 64 : 40) * P); sort_particles(ctx, cotangents); }
+    { KTimer t(ctx, PM_K_SCATTER, 12 * P + r);
+      launch_scatter_density(ctx->xq, ctx->lat, ctx->bins, ctx->creal(0), s); }
+    { KTimer t(ctx, PM_K_FFT_X, r + c); launch_fft_x_r2c(ctx->C[0], ng, cs, 1, cst, ctx->twd, s); }
     { KTimer t(ctx, PM_K_FFT_STRIDED, 2 * c);
-      launch_fft_axis(ctx->C[0], ng, cs, 1, -1, 1, cst, ctx->tw, ng, s); }
+      launch_fft_axis(ctx->C[0], ng, cs, 1, -1, 1, cst, ctx->twd, s); }
     const float* radial;
     { KTimer t(ctx, PM_K_MLP, 0); radial = force_radial(ctx, a); }
     { KTimer t(ctx, PM_K_GRAD_Z, 4 * c);
-      launch_grad_z(ctx->C[0], ctx->C[1], cst, ng, cs, radial, ctx->tw, ng, s); }
+      launch_grad_z(ctx->C[0], ctx->C[1], cst, ng, cs, radial, ctx->twd, s); }
     { KTimer t(ctx, PM_K_FFT_STRIDED, 6 * c);
-      launch_fft_axis(ctx->C[1], ng, cs, 1, 1, 3, cst, ctx->tw, ng, s); }
-    { KTimer t(ctx, PM_K_FFT_X, 3 * (r + c)); launch_fft_x_c2r(ctx->C[1], ng, cs, 3, cst, ctx->tw, ng, s); }
+      launch_fft_axis(ctx->C[1], ng, cs, 1, 1, 3, cst, ctx->twd, s); }
+    { KTimer t(ctx, PM_K_FFT_X, 3 * (r + c)); launch_fft_x_c2r(ctx->C[1], ng, cs, 3, cst, ctx->twd, s); }
 }
 
 // delta_bar (real, in C0) = transposed spectral operator applied to the CIC
@@ -324,11 +366,11 @@ void vjp_mesh(pm_ctx* ctx, const uint32_t* xq, const float* v, float coeff, doub
     const int ng = ctx->ng, cs = ctx->cs;
     const long cst = ctx->plan.cplx_elems;
     const double r = mesh_r(ng), c = mesh_c(ng), P = (double)ctx->P;
-    { KTimer t(ctx, PM_K_SCATTER_VEC, 28 * P + 3 * r);
+    { KTimer t(ctx, PM_K_SCATTER_VEC, 24 * P + 3 * r);
       launch_scatter_vec(xq, v, coeff, ctx->lat, ctx->bins, ctx->creal(1), ctx->creal_stride(), s); }
-    { KTimer t(ctx, PM_K_FFT_X, 3 * (r + c)); launch_fft_x_r2c(ctx->C[1], ng, cs, 3, cst, ctx->tw, ng, s); }
+    { KTimer t(ctx, PM_K_FFT_X, 3 * (r + c)); launch_fft_x_r2c(ctx->C[1], ng, cs, 3, cst, ctx->twd, s); }
     { KTimer t(ctx, PM_K_FFT_STRIDED, 6 * c);
-      launch_fft_axis(ctx->C[1], ng, cs, 1, -1, 3, cst, ctx->tw, ng, s); }
+      launch_fft_axis(ctx->C[1], ng, cs, 1, -1, 3, cst, ctx->twd, s); }
     float* fbar = nullptr;
     const float fscale = (float)(ctx->cfg.box / (2.0 * kPi) / std::pow((double)ng, 3.0));
     if (ctx->cfg.filter) {
@@ -337,34 +379,35 @@ void vjp_mesh(pm_ctx* ctx, const uint32_t* xq, const float* v, float coeff, doub
     }
     { KTimer t(ctx, PM_K_GRAD_ADJ_Z, (fbar ? 5 : 4) * c);
       launch_grad_adj_z(ctx->C[1], cst, ctx->C[0], ctx->C[0], ng, cs, ctx->radial_f, fbar, fscale,
-                        ctx->tw, ng, s); }
+                        ctx->twd, s); }
     if (ctx->cfg.filter) {
         KTimer t(ctx, PM_K_MLP, 0);
         launch_mlp_backward(ctx->theta, ng, (float)ctx->cfg.box, (float)a, fbar, ctx->gtheta,
                             ctx->mlp_scratch, mlp_backward_scratch(ng), s);
     }
     { KTimer t(ctx, PM_K_FFT_STRIDED, 2 * c);
-      launch_fft_axis(ctx->C[0], ng, cs, 1, 1, 1, cst, ctx->tw, ng, s); }
-    { KTimer t(ctx, PM_K_FFT_X, r + c); launch_fft_x_c2r(ctx->C[0], ng, cs, 1, cst, ctx->tw, ng, s); }
+      launch_fft_axis(ctx->C[0], ng, cs, 1, 1, 1, cst, ctx->twd, s); }
+    { KTimer t(ctx, PM_K_FFT_X, r + c); launch_fft_x_c2r(ctx->C[0], ng, cs, 1, cst, ctx->twd, s); }
 }
 
 // Zel'dovich displacement (a = 1) of the stored noise with the radial table;
 // leaves s_j as real meshes in C1..C3 (particle-grid geometry) and writes
 // s_out [P][3] and the fixed-point state x = q + D0 s, p = G0 s (each nullable).
-void ic_synthesis(pm_ctx* ctx, const float* radial, float* s_out, uint32_t* xq, int32_t* pq) {
+void ic_synthesis(pm_ctx* ctx, const float* radial, float* s_out, uint32_t* xq, int32_t* pq,
+                  uint32_t* id) {
     hipStream_t s = ctx->stream;
     const int np = ctx->np, cs = ctx->cs_p, ng = ctx->ng;
     const long cst = ctx->plan.cplx_elems;
     const long rp = 2L * cs;
     KTimer t(ctx, PM_K_OTHER, 0);
     launch_to_pitched(ctx->noise, ctx->creal(0), np, rp, 1.f, s);
-    launch_fft_x_r2c(ctx->C[0], np, cs, 1, cst, ctx->tw, ng, s);
-    launch_fft_axis(ctx->C[0], np, cs, 1, -1, 1, cst, ctx->tw, ng, s);
-    launch_grad_z(ctx->C[0], ctx->C[1], cst, np, cs, radial, ctx->tw, ng, s);
-    launch_fft_axis(ctx->C[1], np, cs, 1, 1, 3, cst, ctx->tw, ng, s);
-    launch_fft_x_c2r(ctx->C[1], np, cs, 3, cst, ctx->tw, ng, s);
+    launch_fft_x_r2c(ctx->C[0], np, cs, 1, cst, ctx->twd, s);
+    launch_fft_axis(ctx->C[0], np, cs, 1, -1, 1, cst, ctx->twd, s);
+    launch_grad_z(ctx->C[0], ctx->C[1], cst, np, cs, radial, ctx->twd, s);
+    launch_fft_axis(ctx->C[1], np, cs, 1, 1, 3, cst, ctx->twd, s);
+    launch_fft_x_c2r(ctx->C[1], np, cs, 3, cst, ctx->twd, s);
     launch_ic_state(ctx->creal(1), ctx->creal_stride(), rp, (float)ctx->sched.D0,
-                    (float)ctx->sched.G0, ctx->lat, xq, pq, s_out, s);
+                    (float)ctx->sched.G0, ctx->lat, xq, pq, id, s_out, s);
 }
 
 // dL/dnoise = transpose of the Zel'dovich synthesis applied to s_bar [P][3].
@@ -375,12 +418,12 @@ void ic_transpose(pm_ctx* ctx, const float* s_bar, float* g_noise) {
     const long rp = 2L * cs;
     KTimer t(ctx, PM_K_OTHER, 0);
     launch_deinterleave(s_bar, ctx->creal(1), ctx->creal_stride(), np, rp, s);
-    launch_fft_x_r2c(ctx->C[1], np, cs, 3, cst, ctx->tw, ng, s);
-    launch_fft_axis(ctx->C[1], np, cs, 1, -1, 3, cst, ctx->tw, ng, s);
+    launch_fft_x_r2c(ctx->C[1], np, cs, 3, cst, ctx->twd, s);
+    launch_fft_axis(ctx->C[1], np, cs, 1, -1, 3, cst, ctx->twd, s);
     launch_grad_adj_z(ctx->C[1], cst, ctx->C[0], ctx->C[0], np, cs, ctx->radial_ic, nullptr, 0.f,
-                      ctx->tw, ng, s);
-    launch_fft_axis(ctx->C[0], np, cs, 1, 1, 1, cst, ctx->tw, ng, s);
-    launch_fft_x_c2r(ctx->C[0], np, cs, 1, cst, ctx->tw, ng, s);
+                      ctx->twd, s);
+    launch_fft_axis(ctx->C[0], np, cs, 1, 1, 1, cst, ctx->twd, s);
+    launch_fft_x_c2r(ctx->C[0], np, cs, 1, cst, ctx->twd, s);
     launch_from_pitched(ctx->creal(0), g_noise, np, rp, s);
 }
 
@@ -487,6 +530,12 @@ int pm_init(const pm_config* cfg, const pm_cosmology* cosmo, void* workspace, si
     ctx->pq = ctx->at<int32_t>(p.mom);
     ctx->xi = ctx->at<float>(p.xi);
     ctx->pi = ctx->at<float>(p.pi);
+    ctx->xq_alt = ctx->at<uint32_t>(p.disp2);
+    ctx->pq_alt = ctx->at<int32_t>(p.mom2);
+    ctx->xi_alt = ctx->at<float>(p.xi2);
+    ctx->pi_alt = ctx->at<float>(p.pi2);
+    ctx->id = ctx->at<uint32_t>(p.id);
+    ctx->id_alt = ctx->at<uint32_t>(p.id2);
     ctx->fin_x = ctx->at<uint32_t>(p.fin_disp);
     ctx->fin_p = ctx->at<int32_t>(p.fin_mom);
     ctx->s_ic = ctx->at<float>(p.s_ic);
@@ -497,6 +546,8 @@ int pm_init(const pm_config* cfg, const pm_cosmology* cosmo, void* workspace, si
     ctx->radial_ic = ctx->at<float>(p.radial_ic);
     ctx->radial_ic_dom = ctx->at<float>(p.radial_ic_dom);
     ctx->tw = ctx->at<float2>(p.tw);
+    ctx->tw_stages = ctx->at<float2>(p.tw_stages);
+    ctx->twd = Twiddles{ctx->tw, ctx->ng, ctx->tw_stages};
     ctx->partials = ctx->at<double>(p.partials);
     ctx->sums = ctx->at<double>(p.sums);
     ctx->maxbits = ctx->at<unsigned>(p.maxbits);
@@ -529,7 +580,6 @@ int pm_init(const pm_config* cfg, const pm_cosmology* cosmo, void* workspace, si
     ctx->bins.offsets = ctx->at<uint32_t>(p.offsets);
     ctx->bins.keys = ctx->at<uint32_t>(p.keys);
     ctx->bins.ranks = ctx->at<uint32_t>(p.ranks);
-    ctx->bins.perm = ctx->at<uint32_t>(p.perm);
     ctx->bins.scan_tmp = ctx->at<uint32_t>(p.scan_tmp);
     std::memset(&ctx->stats, 0, sizeof(ctx->stats));
     ctx->stats.workspace_bytes = p.total;
@@ -590,12 +640,11 @@ int pm_forward(pm_ctx* ctx, const float* noise, float* disp_out, float* mom_out,
     const pm_config& c = ctx->cfg;
     const Schedule& sc = ctx->sched;
     const int N = c.n_steps;
-    const size_t vec = (size_t)ctx->P * 3 * sizeof(uint32_t);
-    hipEventRecord(ctx->ev[0], s);
+    (void)hipEventRecord(ctx->ev[0], s);
     PM_TRY(copy_d2d(ctx, ctx->noise, noise, (size_t)ctx->P * sizeof(float)));
-    ic_synthesis(ctx, ctx->radial_ic, ctx->s_ic, ctx->xq, ctx->pq);
+    ic_synthesis(ctx, ctx->radial_ic, ctx->s_ic, ctx->xq, ctx->pq, ctx->id);
     for (int n = 0; n <= N; ++n) {
-        compute_force(ctx, ctx->xq, sc.a[n]);
+        compute_force(ctx, sc.a[n], false);
         const double kick = (n > 0 ? sc.kick_b[n - 1] : 0.0) + (n < N ? sc.kick_a[n] : 0.0);
         uint32_t* ckx = nullptr;
         int32_t* ckp = nullptr;
@@ -605,21 +654,22 @@ int pm_forward(pm_ctx* ctx, const float* noise, float* disp_out, float* mom_out,
             ckp = reinterpret_cast<int32_t*>(ckx + 3 * ctx->P);
         }
         KTimer t(ctx, PM_K_GATHER, (ckx ? 72.0 : 48.0) * ctx->P + 3 * mesh_r(ctx->ng));
-        launch_gather_kick_drift(ctx->xq, ctx->pq, ctx->creal(1), ctx->creal_stride(), ctx->lat,
-                                 (float)kick, n < N ? (float)sc.drift[n] : 0.f, n < N, ckx, ckp, s);
+        launch_gather_kick_drift(ctx->xq, ctx->pq, ctx->id, ctx->creal(1), ctx->creal_stride(),
+                                 ctx->lat, ctx->bins, (float)kick,
+                                 n < N ? (float)sc.drift[n] : 0.f, n < N, ckx, ckp, s);
     }
-    PM_TRY(copy_d2d(ctx, ctx->fin_x, ctx->xq, vec));
-    PM_TRY(copy_d2d(ctx, ctx->fin_p, ctx->pq, vec));
     {
         KTimer t(ctx, PM_K_OTHER, 0);
-        launch_from_fixed(ctx->xq, ctx->pq, ctx->lat, disp_out, mom_out, s);
+        // final state in lattice order (private copy for the adjoint) and outputs
+        launch_state_to_lattice(ctx->xq, ctx->pq, ctx->id, ctx->P, ctx->fin_x, ctx->fin_p, s);
+        launch_from_fixed(ctx->xq, ctx->pq, ctx->id, ctx->lat, disp_out, mom_out, s);
         if (dens) {
-            launch_bin(ctx->xq, ctx->lat, ctx->bins, s);
+            sort_particles(ctx, false);
             launch_scatter_density(ctx->xq, ctx->lat, ctx->bins, ctx->creal(0), s);
             launch_from_pitched(ctx->creal(0), dens, ctx->ng, ctx->lat.rp, s);
         }
     }
-    hipEventRecord(ctx->ev[1], s);
+    (void)hipEventRecord(ctx->ev[1], s);
     PM_TRY(ctx->hip_check("pm_forward"));
     ctx->have_forward = true;
     return PM_OK;
@@ -644,32 +694,33 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
     const float mass = ctx->mass();
     const double bytes_unkick = 72.0 * P + 3 * mesh_r(ctx->ng);
     const double bytes_wgrad = 84.0 * P + mesh_r(ctx->ng);
-    hipEventRecord(ctx->ev[2], s);
+    (void)hipEventRecord(ctx->ev[2], s);
     PM_TRY(copy_d2d(ctx, ctx->xq, ctx->fin_x, vec));
     PM_TRY(copy_d2d(ctx, ctx->pq, ctx->fin_p, vec));
+    launch_iota(ctx->id, P, s);   // records start in lattice order
     launch_zero(ctx->sums, (2 * (size_t)N + 2 + kExtraSlots) * sizeof(double), s);
     launch_zero(ctx->maxbits, kExtraSlots * sizeof(unsigned), s);
     if (c.filter) launch_zero(ctx->gtheta, kNParam * sizeof(float), s);
     if (g_mom) PM_TRY(copy_d2d(ctx, ctx->pi, g_mom, vec));
     else launch_zero(ctx->pi, vec, s);
 
-    // seed at x_N: xi = dL/dx_N (+ m grad w . dL/ddelta)
-    compute_force(ctx, ctx->xq, sc.a[N]);
+    // seed at x_N: xi = dL/dx_N (lattice order), sorted with the state by the
+    // force evaluation, then + m grad w . dL/ddelta
+    if (g_disp) PM_TRY(copy_d2d(ctx, ctx->xi, g_disp, vec));
+    else launch_zero(ctx->xi, vec, s);
+    compute_force(ctx, sc.a[N], true);
+    const int nbt = (int)gather_blocks(ctx->bins);
     if (g_dens) {
-        KTimer t(ctx, PM_K_WGRAD, 36.0 * P + mesh_r(ctx->ng));
-        launch_wgrad(g_dens, ctx->ng, mass, ctx->xq, ctx->pq, ctx->xi, ctx->pi, g_disp, ctx->lat,
-                     0.f, 0, nullptr, nb, s);
-    } else if (g_disp) {
-        PM_TRY(copy_d2d(ctx, ctx->xi, g_disp, vec));
-    } else {
-        launch_zero(ctx->xi, vec, s);
+        KTimer t(ctx, PM_K_WGRAD, 24.0 * P + mesh_r(ctx->ng));
+        launch_wgrad(g_dens, ctx->ng, mass, ctx->xq, ctx->pq, ctx->xi, ctx->pi, ctx->lat,
+                     ctx->bins, 0.f, 2, nullptr, s);
     }
     {
         KTimer t(ctx, PM_K_UNKICK_VJP, bytes_unkick);
         launch_unkick_vjp(ctx->xq, ctx->pq, ctx->creal(1), ctx->creal_stride(), ctx->lat,
-                          (float)sc.kick_b[N - 1], ctx->pi, ctx->xi, ctx->partials, nb, s);
+                          ctx->bins, (float)sc.kick_b[N - 1], ctx->pi, ctx->xi, ctx->partials, s);
     }
-    launch_reduce(ctx->partials, nb, ctx->sums, slotS + N, s);
+    launch_reduce(ctx->partials, nbt, ctx->sums, slotS + N, s);
 
     int nck = 0;
     for (int n = N - 1; n >= 0; --n) {
@@ -679,65 +730,73 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
         {
             KTimer t(ctx, PM_K_WGRAD, bytes_wgrad);
             launch_wgrad(ctx->creal(0), ctx->lat.rp, mass, ctx->xq, ctx->pq, ctx->xi, ctx->pi,
-                         nullptr, ctx->lat, (float)sc.drift[n], 1, ctx->partials, nb, s);
+                         ctx->lat, ctx->bins, (float)sc.drift[n], 1, ctx->partials, s);
         }
-        launch_reduce(ctx->partials, nb, ctx->sums, slotD + n, s);
+        launch_reduce(ctx->partials, nbt, ctx->sums, slotD + n, s);
         // checkpoint: compare the reconstructed (x_n, p_{n+1/2}) and reset to it
         if (c.checkpoint_every > 0 && n > 0 && n % c.checkpoint_every == 0) {
             const int slot = n / c.checkpoint_every - 1;
             const uint32_t* ckx = ctx->ckpt + (size_t)slot * 6 * P;
-            launch_recon_err(ctx->xq, ckx, ctx->lat, ctx->partials, nb, ctx->maxbits + 2 + nck, s);
+            launch_recon_err(ctx->xq, ctx->id, ckx, ctx->lat, ctx->partials, nb,
+                             ctx->maxbits + 2 + nck, s);
             launch_reduce(ctx->partials, nb, ctx->sums, xCk + nck, s);
+            // reset to the stored (lattice-order) state; cotangents to lattice order
             PM_TRY(copy_d2d(ctx, ctx->xq, ckx, vec));
             PM_TRY(copy_d2d(ctx, ctx->pq, ckx + 3 * P, vec));
+            launch_permute_by_id(ctx->xi, ctx->id, ctx->xi_alt, P, 1, s);
+            launch_permute_by_id(ctx->pi, ctx->id, ctx->pi_alt, P, 1, s);
+            std::swap(ctx->xi, ctx->xi_alt);
+            std::swap(ctx->pi, ctx->pi_alt);
+            launch_iota(ctx->id, P, s);
             ++nck;
         }
         // recompute F(x_n); un-kick and (i) at x_n
-        compute_force(ctx, ctx->xq, sc.a[n]);
+        compute_force(ctx, sc.a[n], true);
         const double c0 = (n > 0 ? sc.kick_b[n - 1] : 0.0) + sc.kick_a[n];
         {
             KTimer t(ctx, PM_K_UNKICK_VJP, bytes_unkick);
             launch_unkick_vjp(ctx->xq, ctx->pq, ctx->creal(1), ctx->creal_stride(), ctx->lat,
-                              (float)c0, ctx->pi, ctx->xi, ctx->partials, nb, s);
+                              ctx->bins, (float)c0, ctx->pi, ctx->xi, ctx->partials, s);
         }
-        launch_reduce(ctx->partials, nb, ctx->sums, slotS + n, s);
+        launch_reduce(ctx->partials, nbt, ctx->sums, slotS + n, s);
     }
     // (ii) + (iii) at x_0
     vjp_mesh(ctx, ctx->xq, ctx->pi, (float)sc.kick_a[0], sc.a[0]);
     {
         KTimer t(ctx, PM_K_WGRAD, 36.0 * P + mesh_r(ctx->ng));
-        launch_wgrad(ctx->creal(0), ctx->lat.rp, mass, ctx->xq, ctx->pq, ctx->xi, ctx->pi, nullptr,
-                     ctx->lat, 0.f, 2, nullptr, nb, s);
+        launch_wgrad(ctx->creal(0), ctx->lat.rp, mass, ctx->xq, ctx->pq, ctx->xi, ctx->pi,
+                     ctx->lat, ctx->bins, 0.f, 2, nullptr, s);
     }
 
     // ICs: x_0 = q + D0 s, p_0 = G0 s.  Reconstruction check against the ICs.
-    ic_synthesis(ctx, ctx->radial_ic, ctx->s_ic, nullptr, nullptr);
+    ic_synthesis(ctx, ctx->radial_ic, ctx->s_ic, nullptr, nullptr, nullptr);
     {
         KTimer t(ctx, PM_K_OTHER, 0);
         launch_ic_check(ctx->creal(1), ctx->creal_stride(), 2L * ctx->cs_p, (float)sc.D0,
-                        (float)sc.G0, ctx->lat, ctx->xq, ctx->pq, ctx->partials, nb, ctx->maxbits, s);
+                        (float)sc.G0, ctx->lat, ctx->xq, ctx->pq, ctx->id, ctx->partials, nb,
+                        ctx->maxbits, s);
         launch_reduce(ctx->partials, nb, ctx->sums, xIc, s);
         launch_reduce(ctx->partials + nb, nb, ctx->sums, xIcMom, s);
         launch_reduce(ctx->partials + 2 * nb, nb, ctx->sums, xIcMomRef, s);
-        launch_dot3(ctx->xi, ctx->s_ic, P, ctx->partials, nb, s);
+        launch_dot3(ctx->xi, ctx->s_ic, P, ctx->partials, nb, s, ctx->id);
         launch_reduce(ctx->partials, nb, ctx->sums, xD0, s);
-        launch_dot3(ctx->pi, ctx->s_ic, P, ctx->partials, nb, s);
+        launch_dot3(ctx->pi, ctx->s_ic, P, ctx->partials, nb, s, ctx->id);
         launch_reduce(ctx->partials, nb, ctx->sums, xG0, s);
-        // s_bar = D0 xi + G0 pi
-        launch_axpby(ctx->tmpv, ctx->xi, (float)sc.D0, ctx->pi, (float)sc.G0, 3 * P, s);
+        // s_bar = D0 xi + G0 pi, in lattice order
+        launch_axpby_scatter(ctx->tmpv, ctx->xi, (float)sc.D0, ctx->pi, (float)sc.G0, ctx->id, P, s);
         launch_dot3(ctx->tmpv, ctx->s_ic, P, ctx->partials, nb, s);
         launch_reduce(ctx->partials, nb, ctx->sums, xSig, s);
     }
     ic_transpose(ctx, ctx->tmpv, g_noise);
     // Omega_m dependence of P(k): s' = synthesis with d radial / d Omega_m
-    ic_synthesis(ctx, ctx->radial_ic_dom, ctx->xi, nullptr, nullptr);
+    ic_synthesis(ctx, ctx->radial_ic_dom, ctx->xi_alt, nullptr, nullptr, nullptr);
     {
         KTimer t(ctx, PM_K_OTHER, 0);
-        launch_dot3(ctx->tmpv, ctx->xi, P, ctx->partials, nb, s);
+        launch_dot3(ctx->tmpv, ctx->xi_alt, P, ctx->partials, nb, s);
         launch_reduce(ctx->partials, nb, ctx->sums, xOm, s);
     }
     if (g_filter) PM_TRY(copy_d2d(ctx, g_filter, ctx->gtheta, kNParam * sizeof(float)));
-    hipEventRecord(ctx->ev[3], s);
+    (void)hipEventRecord(ctx->ev[3], s);
     PM_TRY(ctx->hip_check("pm_adjoint"));
 
     // scalar results (synchronises)
@@ -781,7 +840,7 @@ int pm_loss_mse(pm_ctx* ctx, const float* dens, const float* target, float* g_de
     PM_TRY(ctx_check(ctx));
     if (!dens || !target) return ctx->fail(PM_EINVAL, "dens and target are required");
     const long n3 = (long)ctx->ng * ctx->ng * ctx->ng;
-    const int nb = particle_blocks(n3);
+    const int nb = std::min(particle_blocks(n3), 4096);
     launch_mse(dens, target, g_dens, n3, ctx->partials, nb, ctx->stream);
     PM_TRY(ctx->hip_check("pm_loss_mse"));
     if (loss) {
@@ -803,7 +862,7 @@ int pm_power_spectrum(pm_ctx* ctx, const float* dens, int32_t n_bins, double* k_
     hipStream_t s = ctx->stream;
     const int ng = ctx->ng;
     launch_to_pitched(dens, ctx->creal(0), ng, ctx->lat.rp, 1.f, s);
-    launch_fft3_r2c(ctx->C[0], ng, ctx->cs, 1, ctx->plan.cplx_elems, ctx->tw, ng, s);
+    launch_fft3_r2c(ctx->C[0], ng, ctx->cs, 1, ctx->plan.cplx_elems, ctx->twd, s);
     launch_zero(ctx->pkbins, 3 * (size_t)n_bins * sizeof(double), s);
     launch_pk_bin(ctx->C[0], ng, ctx->cs, n_bins, ctx->pkbins, s);
     PM_TRY(ctx->hip_check("pm_power_spectrum"));
@@ -824,8 +883,8 @@ int pm_power_spectrum(pm_ctx* ctx, const float* dens, int32_t n_bins, double* k_
 int pm_density(pm_ctx* ctx, const float* disp, float* dens) {
     PM_TRY(ctx_check(ctx));
     if (!disp || !dens) return ctx->fail(PM_EINVAL, "disp and dens are required");
-    launch_to_fixed(disp, ctx->xq, ctx->lat, ctx->stream);
-    launch_bin(ctx->xq, ctx->lat, ctx->bins, ctx->stream);
+    launch_to_fixed(disp, ctx->xq, ctx->id, ctx->lat, ctx->stream);
+    sort_particles(ctx, false);
     launch_scatter_density(ctx->xq, ctx->lat, ctx->bins, ctx->creal(0), ctx->stream);
     launch_from_pitched(ctx->creal(0), dens, ctx->ng, ctx->lat.rp, ctx->stream);
     return ctx->hip_check("pm_density");
@@ -835,9 +894,10 @@ int pm_force(pm_ctx* ctx, const float* disp, double a, float* force) {
     PM_TRY(ctx_check(ctx));
     if (!disp || !force) return ctx->fail(PM_EINVAL, "disp and force are required");
     if (ctx->cfg.filter && !ctx->have_filter) return ctx->fail(PM_ESTATE, "pm_set_filter not called");
-    launch_to_fixed(disp, ctx->xq, ctx->lat, ctx->stream);
-    compute_force(ctx, ctx->xq, a);
-    launch_gather_force(ctx->xq, ctx->creal(1), ctx->creal_stride(), ctx->lat, force, ctx->stream);
+    launch_to_fixed(disp, ctx->xq, ctx->id, ctx->lat, ctx->stream);
+    compute_force(ctx, a, false);
+    launch_gather_force(ctx->xq, ctx->id, ctx->creal(1), ctx->creal_stride(), ctx->lat, ctx->bins,
+                        force, ctx->stream);
     return ctx->hip_check("pm_force");
 }
 
@@ -846,16 +906,18 @@ int pm_force_vjp(pm_ctx* ctx, const float* disp, double a, const float* v, float
     if (!disp || !v || !xi) return ctx->fail(PM_EINVAL, "disp, v and xi are required");
     if (ctx->cfg.filter && !ctx->have_filter) return ctx->fail(PM_ESTATE, "pm_set_filter not called");
     hipStream_t s = ctx->stream;
-    const int nb = particle_blocks(ctx->P);
-    launch_to_fixed(disp, ctx->xq, ctx->lat, s);
-    compute_force(ctx, ctx->xq, a);
-    launch_zero(xi, (size_t)ctx->P * 3 * sizeof(float), s);
-    launch_unkick_vjp(ctx->xq, nullptr, ctx->creal(1), ctx->creal_stride(), ctx->lat, 1.f, v, xi,
-                      nullptr, nb, s);
+    launch_to_fixed(disp, ctx->xq, ctx->id, ctx->lat, s);
+    compute_force(ctx, a, false);
+    // v and xi in the records' (sorted) order
+    launch_permute_by_id(v, ctx->id, ctx->pi, ctx->P, 0, s);
+    launch_zero(ctx->xi, (size_t)ctx->P * 3 * sizeof(float), s);
+    launch_unkick_vjp(ctx->xq, nullptr, ctx->creal(1), ctx->creal_stride(), ctx->lat, ctx->bins,
+                      1.f, ctx->pi, ctx->xi, nullptr, s);
     if (ctx->cfg.filter) launch_zero(ctx->gtheta, kNParam * sizeof(float), s);
-    vjp_mesh(ctx, ctx->xq, v, 1.f, a);
-    launch_wgrad(ctx->creal(0), ctx->lat.rp, ctx->mass(), ctx->xq, nullptr, xi, nullptr, nullptr,
-                 ctx->lat, 0.f, 2, nullptr, nb, s);
+    vjp_mesh(ctx, ctx->xq, ctx->pi, 1.f, a);
+    launch_wgrad(ctx->creal(0), ctx->lat.rp, ctx->mass(), ctx->xq, nullptr, ctx->xi, nullptr,
+                 ctx->lat, ctx->bins, 0.f, 2, nullptr, s);
+    launch_permute_by_id(ctx->xi, ctx->id, xi, ctx->P, 1, s);
     return ctx->hip_check("pm_force_vjp");
 }
 
@@ -865,7 +927,7 @@ int pm_fft_r2c(pm_ctx* ctx, const float* real, float* spec) {
     hipStream_t s = ctx->stream;
     const int ng = ctx->ng, h = ng / 2 + 1;
     launch_to_pitched(real, ctx->creal(0), ng, ctx->lat.rp, 1.f, s);
-    launch_fft3_r2c(ctx->C[0], ng, ctx->cs, 1, ctx->plan.cplx_elems, ctx->tw, ng, s);
+    launch_fft3_r2c(ctx->C[0], ng, ctx->cs, 1, ctx->plan.cplx_elems, ctx->twd, s);
     if (hipMemcpy2DAsync(spec, h * sizeof(float2), ctx->C[0], ctx->cs * sizeof(float2),
                          h * sizeof(float2), (size_t)ng * ng, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return ctx->fail(PM_EHIP, "copy of the spectrum failed");
@@ -880,7 +942,7 @@ int pm_fft_c2r(pm_ctx* ctx, const float* spec, float* real) {
     if (hipMemcpy2DAsync(ctx->C[0], ctx->cs * sizeof(float2), spec, h * sizeof(float2),
                          h * sizeof(float2), (size_t)ng * ng, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return ctx->fail(PM_EHIP, "copy of the spectrum failed");
-    launch_fft3_c2r(ctx->C[0], ng, ctx->cs, 1, ctx->plan.cplx_elems, ctx->tw, ng, s);
+    launch_fft3_c2r(ctx->C[0], ng, ctx->cs, 1, ctx->plan.cplx_elems, ctx->twd, s);
     launch_from_pitched(ctx->creal(0), real, ng, ctx->lat.rp, s);
     return ctx->hip_check("pm_fft_c2r");
 }
