@@ -108,9 +108,11 @@ void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, const Records& re
 // L.rp; every cell written once (no pre-zeroing), deterministic.
 void launch_scatter_density(const uint32_t* xq, const Lattice& L, const Bins& b, float* mesh,
                             hipStream_t s);
-// out_j = Sum_p coeff v_{p,j} w(x_p, node) for j = 0..2 into meshes out + j*outStride.
-void launch_scatter_vec(const uint32_t* xq, const float* v, float coeff, const Lattice& L,
-                        const Bins& b, float* out, long outStride, hipStream_t s);
+// out_j = Sum_p coeff v_{p,j} w(x_p, node) for j = 0..2 into meshes out + j*outStride
+// (64-bit fixed point, bitwise reproducible); vmax_scratch is one device word.
+void launch_scatter_vec(const uint32_t* xq, const float* v, float coeff, unsigned* vmax_scratch,
+                        const Lattice& L, const Bins& b, float* out, long outStride,
+                        hipStream_t s);
 
 // Gathers: one work-group per tile of the current bins (particles must be
 // sorted by those bins); partials (nullable) get one FP64 value per tile.

@@ -26,6 +26,7 @@
 // not depend on the order of the LDS atomics (bitwise reproducible).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "kernels.h"
@@ -268,20 +269,23 @@ __device__ __forceinline__ void tile_range(int r, int tx, int ty, int tz, int nt
 
 constexpr int kRanges = 20;
 
+// One work-group per tile.  Densities accumulate mass * w in 64-bit fixed
+// point with 2^32 units; the vector scatter (VEC) accumulates coeff * v_j * w
+// one component at a time, in 64-bit fixed point whose unit is chosen from
+// max |coeff * v| and the particle count so that no sum can overflow.  Integer
+// LDS atomics are both order-independent (bitwise reproducible results) and far
+// faster on gfx950 than floating-point LDS atomics.
 template <int T, bool VEC>
 __global__ void __launch_bounds__(kBlock)
 k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, float coeff,
-               Lattice L, int nt, const uint32_t* __restrict__ offsets, float* __restrict__ out,
-               long outStride) {
+               const unsigned* __restrict__ vmax_bits, Lattice L, int nt,
+               const uint32_t* __restrict__ offsets, float* __restrict__ out, long outStride) {
     constexpr int T3 = T * T * T;
-    constexpr int NACC = VEC ? 3 : 1;
-    using Acc = typename std::conditional<VEC, float, unsigned long long>::type;
-    __shared__ Acc acc[NACC * T3];
+    __shared__ unsigned long long acc[T3];
     __shared__ uint32_t rs[kRanges], pre[kRanges + 1];
     const uint32_t tile = xcd_block(blockIdx.x, gridDim.x);
     const int tx = compact3(tile >> 2), ty = compact3(tile >> 1), tz = compact3(tile);
     const int lo[3] = {tx * T, ty * T, tz * T};
-    for (int c = threadIdx.x; c < NACC * T3; c += kBlock) acc[c] = (Acc)0;
     if (threadIdx.x < kRanges) {
         uint32_t b, e;
         tile_range(threadIdx.x, tx, ty, tz, nt, offsets, &b, &e);
@@ -295,23 +299,35 @@ k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, 
     }
     __syncthreads();
     const int mask = L.ng - 1;
-    const float mass = (float)(L.ratio * L.ratio * L.ratio);
-    // one flat index space over the 20 ranges, so every lane has work
+    double scale = kFix, inv_scale = 1.0 / kFix;
+    float amp = (float)(L.ratio * L.ratio * L.ratio);   // mass
+    if constexpr (VEC) {
+        // |Sum| <= P max|coeff v|: unit 2^-e with 2^e <= 2^62 / (P max|coeff v|)
+        const double vmax = (double)fabsf(coeff) * (double)__uint_as_float(*vmax_bits);
+        const double P = (double)L.np * L.np * L.np;
+        int e = 0;
+        if (vmax > 0.0) {
+            frexp(P * vmax, &e);
+            e = 61 - e;
+        }
+        scale = ldexp(1.0, e);
+        inv_scale = ldexp(1.0, -e);
+        amp = coeff;
+    }
     const uint32_t total = pre[kRanges];
-    for (uint32_t k = threadIdx.x; k < total; k += kBlock) {
-        int r = 0;
-        while (pre[r + 1] <= k) ++r;
-        const long p = rs[r] + (k - pre[r]);   // particles are stored in bin order
-        {
+    constexpr int NC = VEC ? 3 : 1;
+    for (int comp = 0; comp < NC; ++comp) {
+        for (int c = threadIdx.x; c < T3; c += kBlock) acc[c] = 0ull;
+        __syncthreads();
+        // one flat index space over the 20 ranges, so every lane has work
+        for (uint32_t k = threadIdx.x; k < total; k += kBlock) {
+            int r = 0;
+            while (pre[r + 1] <= k) ++r;
+            const long p = rs[r] + (k - pre[r]);   // particles are stored in bin order
             int ii[3];
             float t[3];
             locate(xq + 3 * p, L, ii, t);
-            float v0 = 0.f, v1 = 0.f, v2 = 0.f;
-            if constexpr (VEC) {
-                v0 = coeff * vals[3 * p];
-                v1 = coeff * vals[3 * p + 1];
-                v2 = coeff * vals[3 * p + 2];
-            }
+            const float val = VEC ? amp * vals[3 * p + comp] : amp;
 #pragma unroll
             for (int c0 = 0; c0 < 2; ++c0) {
                 int l0 = ((ii[0] + c0) & mask) - lo[0];
@@ -331,31 +347,32 @@ k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, 
                         if (l2 >= T) continue;
                         const float w = w01 * (c2 ? t[2] : 1.f - t[2]);
                         const int cell = (l0 * T + l1) * T + l2;
-                        if constexpr (VEC) {
-                            atomicAdd(&acc[cell], w * v0);
-                            atomicAdd(&acc[T3 + cell], w * v1);
-                            atomicAdd(&acc[2 * T3 + cell], w * v2);
-                        } else {
-                            const double q = (double)(w * mass) * kFix;
-                            atomicAdd(&acc[cell], (unsigned long long)__double2ll_rn(q));
-                        }
+                        const double q = (double)(w * val) * scale;
+                        atomicAdd(&acc[cell], (unsigned long long)__double2ll_rn(q));
                     }
                 }
             }
         }
-    }
-    __syncthreads();
-    for (int c = threadIdx.x; c < T3; c += kBlock) {
-        const int l2 = c % T, l1 = (c / T) % T, l0 = c / (T * T);
-        const long o = ((long)(lo[0] + l0) * L.ng + (lo[1] + l1)) * L.rp + lo[2] + l2;
-        if constexpr (VEC) {
-            out[o] = acc[c];
-            out[outStride + o] = acc[T3 + c];
-            out[2 * outStride + o] = acc[2 * T3 + c];
-        } else {
-            out[o] = (float)((double)(long long)acc[c] * (1.0 / kFix) - 1.0);
+        __syncthreads();
+        float* o = out + comp * outStride;
+        for (int c = threadIdx.x; c < T3; c += kBlock) {
+            const int l2 = c % T, l1 = (c / T) % T, l0 = c / (T * T);
+            const long g = ((long)(lo[0] + l0) * L.ng + (lo[1] + l1)) * L.rp + lo[2] + l2;
+            const double v = (double)(long long)acc[c] * inv_scale;
+            o[g] = VEC ? (float)v : (float)(v - 1.0);
         }
+        __syncthreads();
     }
+}
+
+// max |v| over n floats as float bits (non-negative floats order like their bits)
+__global__ void __launch_bounds__(kBlock)
+k_absmax(const float* __restrict__ v, long n, unsigned* __restrict__ out) {
+    float m = 0.f;
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock)
+        m = fmaxf(m, fabsf(v[i]));
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_down(m, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
 }
 
 // ------------------------------------------------------------- gathers
@@ -823,33 +840,39 @@ void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, const Records& re
 }
 
 template <bool VEC>
-static void scatter_dispatch(const uint32_t* xq, const float* v, float coeff, const Lattice& L,
-                             const Bins& b, float* out, long outStride, hipStream_t s) {
+static void scatter_dispatch(const uint32_t* xq, const float* v, float coeff, const unsigned* vmax,
+                             const Lattice& L, const Bins& b, float* out, long outStride,
+                             hipStream_t s) {
     const unsigned ntiles = (unsigned)b.nt * b.nt * b.nt;
     switch (b.tile) {
         case 4:
             hipLaunchKernelGGL((k_scatter_tile<4, VEC>), dim3(ntiles), dim3(kBlock), 0, s, xq, v,
-                               coeff, L, b.nt, b.offsets, out, outStride);
+                               coeff, vmax, L, b.nt, b.offsets, out, outStride);
             break;
         case 8:
             hipLaunchKernelGGL((k_scatter_tile<8, VEC>), dim3(ntiles), dim3(kBlock), 0, s, xq, v,
-                               coeff, L, b.nt, b.offsets, out, outStride);
+                               coeff, vmax, L, b.nt, b.offsets, out, outStride);
             break;
         default:
             hipLaunchKernelGGL((k_scatter_tile<16, VEC>), dim3(ntiles), dim3(kBlock), 0, s, xq, v,
-                               coeff, L, b.nt, b.offsets, out, outStride);
+                               coeff, vmax, L, b.nt, b.offsets, out, outStride);
             break;
     }
 }
 
 void launch_scatter_density(const uint32_t* xq, const Lattice& L, const Bins& b, float* mesh,
                             hipStream_t s) {
-    scatter_dispatch<false>(xq, nullptr, 0.f, L, b, mesh, 0, s);
+    scatter_dispatch<false>(xq, nullptr, 0.f, nullptr, L, b, mesh, 0, s);
 }
 
-void launch_scatter_vec(const uint32_t* xq, const float* v, float coeff, const Lattice& L,
-                        const Bins& b, float* out, long outStride, hipStream_t s) {
-    scatter_dispatch<true>(xq, v, coeff, L, b, out, outStride, s);
+void launch_scatter_vec(const uint32_t* xq, const float* v, float coeff, unsigned* vmax_scratch,
+                        const Lattice& L, const Bins& b, float* out, long outStride,
+                        hipStream_t s) {
+    const long P = (long)L.np * L.np * L.np;
+    launch_zero(vmax_scratch, sizeof(unsigned), s);
+    const long nb = std::min<long>(grid_for(3 * P), 4096);
+    hipLaunchKernelGGL(k_absmax, dim3((unsigned)nb), dim3(kBlock), 0, s, v, 3 * P, vmax_scratch);
+    scatter_dispatch<true>(xq, v, coeff, vmax_scratch, L, b, out, outStride, s);
 }
 
 template <int MODE>

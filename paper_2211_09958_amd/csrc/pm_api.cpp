@@ -367,7 +367,8 @@ void vjp_mesh(pm_ctx* ctx, const uint32_t* xq, const float* v, float coeff, doub
     const long cst = ctx->plan.cplx_elems;
     const double r = mesh_r(ng), c = mesh_c(ng), P = (double)ctx->P;
     { KTimer t(ctx, PM_K_SCATTER_VEC, 24 * P + 3 * r);
-      launch_scatter_vec(xq, v, coeff, ctx->lat, ctx->bins, ctx->creal(1), ctx->creal_stride(), s); }
+      launch_scatter_vec(xq, v, coeff, ctx->maxbits + kExtraSlots - 1, ctx->lat, ctx->bins,
+                         ctx->creal(1), ctx->creal_stride(), s); }
     { KTimer t(ctx, PM_K_FFT_X, 3 * (r + c)); launch_fft_x_r2c(ctx->C[1], ng, cs, 3, cst, ctx->twd, s); }
     { KTimer t(ctx, PM_K_FFT_STRIDED, 6 * c);
       launch_fft_axis(ctx->C[1], ng, cs, 1, -1, 3, cst, ctx->twd, s); }
