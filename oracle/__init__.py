@@ -12,16 +12,16 @@ recovered by reverse time integration, discretize-then-optimize so that the
 gradient follows the same discrete trajectory as the forward run.  The paper
 prints no equations; every formula here is standard published physics written
 out plainly and pinned by the tests under ``tests/`` (closed forms, brute-force
-DFTs, invariants, finite differences).  Readings where the paper is silent are
-listed in DESIGN.md.
+DFTs, invariants, finite differences).  Where the paper is silent, each module's
+docstring states the reading it takes.
 
 Modules
   cosmology  background E(a), linear growth D, G, Eisenstein-Hu no-wiggle
              transfer function, sigma_8 normalisation, KDK coefficients
   mesh       cloud-in-cell scatter/gather/gradient, spectral Poisson force,
-             power spectrum
+             power spectrum and its transpose
   mlp        the 2-64-64-1 SiLU force filter, forward and backward
   pm         initial conditions, KDK time stepping, discrete adjoint over a
              stored trajectory, gradients w.r.t. noise, Omega_m, sigma_8 and
-             filter weights
+             filter weights; the filter-training losses
 """

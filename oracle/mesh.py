@@ -243,3 +243,28 @@ def power_spectrum(delta, box, n_bins=None):
         pk = psum / cnt * box ** 3 / mesh ** 6
         kmean = ksum / cnt * 2.0 * np.pi / box
     return kmean, pk, cnt
+
+
+def power_spectrum_vjp(delta, box, n_bins, g_pk):
+    """Gradient of Sum_b g_pk[b-1] P(k_b) with respect to the real mesh delta.
+
+    From the definition P_b = (box^3 / N^6) (1/N_b) Sum_{k in shell b} |delta_k|^2
+    over the FULL spectrum: d|delta_k|^2 / d delta(x) = 2 Re[conj(delta_k) e^{-ik.x}],
+    so the gradient is 2 Re Sum_k t_k conj(delta_k) e^{-ik.x} with
+    t_k = g_pk[b(k)-1] box^3 / (N^6 N_b), i.e. 2 N^3 Re IDFT(t delta_k) because t is
+    even in k.  Computed with the full complex FFT so that no half-spectrum
+    bookkeeping enters.
+    """
+    delta = np.asarray(delta, dtype=np.float64)
+    mesh = delta.shape[0]
+    _, _, cnt = power_spectrum(delta, box, n_bins)
+    n = np.fft.fftfreq(mesh, d=1.0 / mesh).round()
+    nabs = np.sqrt(n[:, None, None] ** 2 + n[None, :, None] ** 2 + n[None, None, :] ** 2)
+    b = np.floor(nabs + 0.5).astype(np.int64)
+    t = np.zeros(n_bins + 1)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        t[1:] = np.where(cnt > 0, np.asarray(g_pk, dtype=np.float64) * box ** 3
+                         / (mesh ** 6 * cnt), 0.0)
+    tk = np.where(b <= n_bins, t[np.minimum(b, n_bins)], 0.0)
+    dk = np.fft.fftn(delta)
+    return 2.0 * mesh ** 3 * np.real(np.fft.ifftn(tk * dk))

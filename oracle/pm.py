@@ -312,3 +312,36 @@ def mse_loss(dens, target):
     d = np.asarray(dens, dtype=np.float64) - np.asarray(target, dtype=np.float64)
     n = d.size
     return float(np.sum(d * d)) / n, 2.0 * d / n
+
+
+# ------------------------------------------------------- filter-training losses
+#
+# The paper names no training objective for a learned force correction.  The
+# reading taken: a power-spectrum term over the shells up to the Nyquist wave
+# number of the coarse mesh, plus a weighted term on the final particle
+# positions, both against a run of the same initial conditions on a finer mesh.
+
+def pk_loss(dens, pk_target, box, n_bins, weight=1.0):
+    """L = weight * mean_b (P_b / P_b^target - 1)^2 over shells b = 1..n_bins that
+    hold modes and a nonzero target, with P measured by ``mesh.power_spectrum``;
+    returns (L, dL/d dens)."""
+    _, pk, cnt = M.power_spectrum(dens, box, n_bins)
+    pt = np.asarray(pk_target, dtype=np.float64)
+    use = (cnt > 0) & (pt != 0)
+    nb = int(np.count_nonzero(use))
+    r = np.where(use, pk / np.where(use, pt, 1.0) - 1.0, 0.0)
+    loss = weight * float(np.sum(r * r)) / nb
+    g_pk = np.where(use, weight * 2.0 * r / (np.where(use, pt, 1.0) * nb), 0.0)
+    return loss, M.power_spectrum_vjp(dens, box, n_bins, g_pk)
+
+
+def disp_loss(disp, disp_target, box, mesh, weight=1.0):
+    """L = weight * mean_p |x_p - x_p^target|^2 / cell^2 with the periodic
+    minimum-image separation (same lattice point, so x - x' = s - s' wrapped to
+    [-box/2, box/2)); returns (L, dL/d disp)."""
+    d = np.asarray(disp, dtype=np.float64) - np.asarray(disp_target, dtype=np.float64)
+    d = d - box * np.floor(d / box + 0.5)
+    cell = box / mesh
+    n = d.shape[0]
+    return (weight * float(np.sum(d * d)) / (n * cell * cell),
+            weight * 2.0 * d / (n * cell * cell))

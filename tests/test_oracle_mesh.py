@@ -226,3 +226,35 @@ def test_power_spectrum_parseval_and_counts():
     nn = np.sqrt(n[:, None, None] ** 2 + n[None, :, None] ** 2 + n[None, None, :] ** 2)
     b = np.floor(nn + 0.5)
     assert N.sum() == np.sum((b >= 1) & (b <= 20))
+
+
+def test_power_spectrum_vjp_single_mode_closed_form():
+    """For delta = A cos(k.x) with k in shell b alone, d P_b / d delta(x) =
+    2 box^3 delta(x) / (N^3 N_b), N_b counted by enumerating integer vectors."""
+    mesh, box, A = 8, 20.0, 0.3
+    c = (np.arange(mesh) + 0.5) * box / mesh
+    X = np.stack(np.meshgrid(c, c, c, indexing="ij"), axis=-1)
+    n = np.array([1, 2, 0])                      # |n|^2 = 5, shell round(2.236) = 2
+    delta = A * np.cos(X @ (2 * np.pi * n / box))
+    g_pk = np.zeros(4)
+    g_pk[1] = 1.0
+    grad = M.power_spectrum_vjp(delta, box, 4, g_pk)
+    rng = range(-mesh // 2, mesh // 2)
+    nb = sum(1 for v in itertools.product(rng, repeat=3)
+             if np.floor(np.sqrt(v[0] ** 2 + v[1] ** 2 + v[2] ** 2) + 0.5) == 2)
+    expect = 2 * box ** 3 * delta / (mesh ** 3 * nb)
+    assert np.max(np.abs(grad - expect)) < 1e-12 * np.max(np.abs(expect))
+
+
+def test_power_spectrum_vjp_matches_finite_difference():
+    """Sum_b g_b P_b is quadratic in delta, so a central difference is exact up to
+    rounding."""
+    mesh, box, nbins = 8, 10.0, 5
+    d = normal((mesh,) * 3, 41)
+    g_pk = normal(nbins, 42)
+    u = normal((mesh,) * 3, 43)
+    F = lambda x: float(np.dot(g_pk, M.power_spectrum(x, box, nbins)[1]))
+    h = 1e-3
+    fd = (F(d + h * u) - F(d - h * u)) / (2 * h)
+    an = float(np.sum(M.power_spectrum_vjp(d, box, nbins, g_pk) * u))
+    assert abs(fd - an) < 1e-9 * abs(an)

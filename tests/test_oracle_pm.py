@@ -12,7 +12,7 @@ from oracle import cosmology as C
 from oracle import mesh as M
 from oracle import mlp
 from oracle import pm
-from synthetic import Cosmology, Workload, mlp_init, normal, white_noise
+from synthetic import Cosmology, Workload, mlp_init, normal, uniform, white_noise
 
 CO = Cosmology()
 
@@ -186,3 +186,42 @@ def test_ic_transpose_dot_product():
     lhs = np.sum(pm.zeldovich_displacement(w, box, radial) * sb)
     rhs = np.sum(w * pm.zeldovich_transpose(sb, box, radial))
     assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+# ------------------------------------------------------- filter-training losses
+
+def test_pk_loss_gradient_matches_finite_difference():
+    mesh, box, nbins = 8, 16.0, 4
+    d = normal((mesh,) * 3, 51)
+    target = M.power_spectrum(normal((mesh,) * 3, 52), box, nbins)[1]
+    u = normal((mesh,) * 3, 53)
+    L0, g = pm.pk_loss(d, target, box, nbins, weight=0.7)
+    h = 1e-5
+    fd = (pm.pk_loss(d + h * u, target, box, nbins, 0.7)[0]
+          - pm.pk_loss(d - h * u, target, box, nbins, 0.7)[0]) / (2 * h)
+    assert abs(fd - np.sum(g * u)) < 1e-7 * abs(fd)
+    # zero at the target itself
+    assert pm.pk_loss(d, M.power_spectrum(d, box, nbins)[1], box, nbins)[0] < 1e-28
+
+
+def test_pk_loss_value_by_hand():
+    """Doubling the field quadruples every P_b: loss = mean (4 - 1)^2 = 9."""
+    mesh, box, nbins = 8, 16.0, 4
+    d = normal((mesh,) * 3, 54)
+    target = M.power_spectrum(d, box, nbins)[1]
+    assert abs(pm.pk_loss(2 * d, target, box, nbins)[0] - 9.0) < 1e-12
+
+
+def test_disp_loss_periodic_minimum_image():
+    box, mesh, n = 32.0, 16, 50
+    s = uniform((n, 3), 55, -3.0, 3.0)
+    eps = normal((n, 3), 56) * 0.2
+    shifts = np.round(uniform((n, 3), 57, -2.0, 2.0)) * box   # whole box periods
+    L, g = pm.disp_loss(s, s + eps + shifts, box, mesh, weight=0.5)
+    cell = box / mesh
+    assert abs(L - 0.5 * np.sum(eps * eps) / (n * cell * cell)) < 1e-12 * L
+    assert np.max(np.abs(g + 0.5 * 2 * eps / (n * cell * cell))) < 1e-12 * np.max(np.abs(g))
+    # separations near half a box pick the nearer image
+    a = np.array([[0.0, 0.0, 0.0]])
+    b = np.array([[0.6 * box, 0.0, 0.0]])
+    assert abs(pm.disp_loss(a, b, box, mesh)[0] - (0.4 * box / cell) ** 2) < 1e-9
