@@ -24,12 +24,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fwd+adjoint particle-steps/s at 512³/1024³; learned vs plain speed at 2% P(k)"
 PEAK_HBM_GBS = 8000.0
+CPU_STEPS = 10          # oracle sample: about 10-20 s on a 16-core host
 FAMILY_KERNELS = {
     "fft_strided": ["k_fft_strided"], "fft_x": ["k_fft_x_r2c", "k_fft_x_c2r"],
-    "grad_z": ["k_grad_z"], "grad_adj_z": ["k_grad_adj_z"], "scatter": ["k_scatter_tile"],
-    "scatter_vec": ["k_scatter_tile"], "gather": ["k_gather_kick_drift"],
-    "unkick_vjp": ["k_unkick_vjp"], "wgrad": ["k_wgrad"],
-    "bin": ["k_bin_count", "k_scan_local", "k_scan_bsum", "k_scan_add", "k_bin_permute"],
+    "grad_z": ["k_grad_z"], "grad_adj_z": ["k_grad_adj_z"],
+    "scatter": ["k_scatter_tile<16, false>"], "scatter_vec": ["k_scatter_tile<16, true>"],
+    "gather": ["k_gather_tile<16, 0>"], "unkick_vjp": ["k_gather_tile<16, 2>"],
+    "wgrad": ["k_gather_tile<16, 3>"],
+    "bin": ["k_bin_count", "k_scan_local", "k_scan_bsum", "k_scan_add", "k_permute"],
 }
 
 
@@ -51,43 +53,42 @@ def parse():
 def cpu_baseline():
     """The FP64 oracle, as it stands, on a bounded sample of the workload: 64^3
     particles on a 128^3 mesh in a 64 Mpc/h box (the headline's cell size and
-    particle spacing), 2 KDK steps, forward + MSE loss + stored-trajectory adjoint."""
+    particle spacing), CPU_STEPS KDK steps, forward + MSE loss + stored-trajectory adjoint."""
     import numpy as np
     from oracle import mesh as M
     from oracle import pm as opm
     from synthetic import Cosmology, white_noise
     cores = len(os.sched_getaffinity(0))
     M.WORKERS = cores
-    st = opm.Setup(64, 128, 64.0, 2, Cosmology())
+    st = opm.Setup(64, 128, 64.0, CPU_STEPS, Cosmology())
     target = opm.forward(white_noise(64, 1), st).dens
     t0 = time.perf_counter()
     run = opm.forward(white_noise(64, 0), st)
     _, gd = opm.mse_loss(run.dens, target)
     opm.adjoint(run, white_noise(64, 0), g_dens=gd)
     dt = time.perf_counter() - t0
-    return {"value": 64 ** 3 * 2 / dt, "unit": "particle-steps/s", "cores": cores,
+    return {"value": 64 ** 3 * CPU_STEPS / dt, "unit": "particle-steps/s", "cores": cores,
             "kind": "oracle",
             "sample": "64^3 particles, 128^3 mesh, box 64 Mpc/h (same cell size and particle "
-                      "spacing as 512^3/1024^3), 2 KDK steps, fwd + MSE loss + adjoint, FP64; "
+                      f"spacing as 512^3/1024^3), {CPU_STEPS} KDK steps, fwd + MSE loss + adjoint, FP64; "
                       f"scipy.fft with {cores} workers, CIC single-threaded numpy; {dt:.1f} s"}
 
 
-def traffic_for(family):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources."""
+def traffic_for(family, alg_bytes_per_launch):
+    """HBM bytes per launch from the committed rocprofv3 counter summary: the family's
+    measured/algorithmic byte ratio (FETCH_SIZE + WRITE_SIZE, calibrated) times its
+    algorithmic bytes per launch here.  None when the summary is absent or was taken on
+    other kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
+    from paper_2211_09958_amd.rocprof_summary import sources_sha256
     with open(path) as f:
         data = json.load(f)
-    entry = data.get(family)
-    if not entry:
+    entry = data.get("families", {}).get(family)
+    if not entry or entry.get("sources_sha256") != sources_sha256(family):
         return None
-    src = os.path.join(ROOT, "paper_2211_09958_amd", "csrc", entry["source"])
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if sha != entry.get("source_sha256"):
-        return None
-    return entry["hbm_bytes_per_launch"]
+    return entry["measured_over_algorithmic"] * alg_bytes_per_launch
 
 
 def main():
@@ -126,23 +127,29 @@ def main():
         g_noise, g_cosmo, _ = ctx.adjoint(g_dens=g)
         return g_cosmo
 
+    for _ in range(args.warmup):
+        step(pm)
+    torch.cuda.synchronize()
+    pm.reset_stats()
     if args.calib_copy_gib > 0:
+        # a device copy of known size, for calibrating HBM byte counters under a profiler
         n = int(args.calib_copy_gib * 2 ** 30) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
-        step(pm)
-    torch.cuda.synchronize()
-    pm.reset_stats()
+    # one-element uint8 fills mark the timed region for kernel-trace summaries
+    marker = torch.empty(1, dtype=torch.uint8, device="cuda:0")
+    marker.fill_(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         g_cosmo = step(pm)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    marker.fill_(2)
+    torch.cuda.synchronize()
     st = pm.stats()
     value = P * w.n_steps * args.steps / dt
 
@@ -151,7 +158,7 @@ def main():
     f = fams[dom]
     achieved = f["bytes"] / (f["ms"] * 1e-3) / 1e9 if f["ms"] > 0 else 0.0
     per_launch = f["bytes"] / max(f["launches"], 1)
-    traffic = traffic_for(dom)
+    traffic = traffic_for(dom, per_launch)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                 "kernel": dom, "kernel_symbols": FAMILY_KERNELS.get(dom, []),
