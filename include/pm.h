@@ -194,6 +194,28 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens_dev, const float* g_disp_dev,
 int pm_loss_mse(pm_ctx* ctx, const float* dens_dev, const float* target_dev,
                 float* g_dens_dev, double* loss_host);
 
+/* Filter-training losses against a run of the same initial conditions on a finer
+ * mesh (the paper motivates learned corrections of the PM force; the objective
+ * is a reading: power spectrum plus final positions).
+ *
+ * pm_loss_pk: L = weight * mean_b (P_b / pk_target_host[b-1] - 1)^2 over shells
+ *   b = 1..n_bins (1 <= n_bins <= Ng) that hold modes and have a nonzero finite
+ *   target, P_b measured from dens_dev [Ng]^3 exactly as pm_power_spectrum does.
+ *   g_dens_dev [Ng]^3 out = dL/d(dens) (nullable).  loss_host nullable.  Always
+ *   synchronises (the shell sums are read on the host).  PM_EINVAL when no shell
+ *   is usable.  Uses the workspace meshes, so it may run between pm_forward and
+ *   pm_adjoint.
+ * pm_loss_disp: L = weight * mean_p |s_p - t_p|^2 / (box/Ng)^2 over the Np^3
+ *   particles of displacement arrays disp_dev and disp_target_dev ([Np^3][3],
+ *   lattice order; equal lattice points, so the separation is s - t wrapped to
+ *   the periodic minimum image [-box/2, box/2)).  g_disp_dev out = dL/d(disp)
+ *   (nullable).  loss_host nullable; when given the call synchronises. */
+int pm_loss_pk(pm_ctx* ctx, const float* dens_dev, int32_t n_bins,
+               const double* pk_target_host, double weight, double* loss_host,
+               float* g_dens_dev);
+int pm_loss_disp(pm_ctx* ctx, const float* disp_dev, const float* disp_target_dev,
+                 double weight, double* loss_host, float* g_disp_dev);
+
 /* Shell-averaged power spectrum of an [Ng]^3 overdensity: shells
  * b = round(|n|) for b = 1..n_bins, P = (L^3/Ng^6) <|delta_k|^2>, no shot-noise
  * or window correction.  Outputs (host, n_bins each, nullable individually):
@@ -224,12 +246,14 @@ int pm_fft_c2r(pm_ctx* ctx, const float* spec_dev, float* real_dev);
 /* Learned-filter training helpers (filter = 1 configs).
  *   pm_filter_table: table_dev [3 (Ng/2)^2 + 1] = f(|n|^2, a) for the current
  *                    weights
- *   pm_adam: one Adam step on n FP32 parameters in place, moments m_dev,
- *            v_dev (n each), step count t >= 1 (bias correction). */
+ *   pm_adam: one Adam step (Kingma & Ba) on n FP32 parameters in place, on the
+ *            mean of n_grads >= 1 gradients grad_dev [n_grads][n] (a batch of
+ *            runs), moments m_dev, v_dev (n each), step count t >= 1 for the
+ *            bias correction. */
 int pm_filter_table(pm_ctx* ctx, double a, float* table_dev);
-int pm_adam(pm_ctx* ctx, float* param_dev, const float* grad_dev, float* m_dev,
-            float* v_dev, int32_t n, double lr, double beta1, double beta2,
-            double eps, int32_t t);
+int pm_adam(pm_ctx* ctx, float* param_dev, const float* grad_dev, int32_t n_grads,
+            float* m_dev, float* v_dev, int32_t n, double lr, double beta1,
+            double beta2, double eps, int32_t t);
 
 /* Statistics of the context; synchronises the stream when PM_F_TIMING is set.
  * pm_stats_reset clears the per-kernel accumulators. */

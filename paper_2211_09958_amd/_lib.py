@@ -23,7 +23,8 @@ KERNEL_FAMILIES = ("bin", "scatter", "scatter_vec", "fft_x", "fft_strided", "gra
 
 # exported entry points, in the order include/pm.h declares them
 EXPORTS = ("pm_workspace_bytes", "pm_host_tables", "pm_init", "pm_set_cosmology",
-           "pm_set_filter", "pm_forward", "pm_adjoint", "pm_loss_mse", "pm_power_spectrum",
+           "pm_set_filter", "pm_forward", "pm_adjoint", "pm_loss_mse", "pm_loss_pk",
+           "pm_loss_disp", "pm_power_spectrum",
            "pm_density", "pm_force", "pm_force_vjp", "pm_fft_r2c", "pm_fft_c2r",
            "pm_filter_table", "pm_adam", "pm_stats_get", "pm_stats_reset", "pm_destroy",
            "pm_last_error")
@@ -79,6 +80,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "pm_forward": (c_int, [P, P, P, P, P]),
         "pm_adjoint": (c_int, [P, P, P, P, P, P, P]),
         "pm_loss_mse": (c_int, [P, P, P, P, P]),
+        "pm_loss_pk": (c_int, [P, P, c_int32, P, c_double, P, P]),
+        "pm_loss_disp": (c_int, [P, P, P, c_double, P, P]),
         "pm_power_spectrum": (c_int, [P, P, c_int32, P, P, P]),
         "pm_density": (c_int, [P, P, P]),
         "pm_force": (c_int, [P, P, c_double, P]),
@@ -86,7 +89,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "pm_fft_r2c": (c_int, [P, P, P]),
         "pm_fft_c2r": (c_int, [P, P, P]),
         "pm_filter_table": (c_int, [P, c_double, P]),
-        "pm_adam": (c_int, [P, P, P, P, P, c_int32, c_double, c_double, c_double, c_double, c_int32]),
+        "pm_adam": (c_int, [P, P, P, c_int32, P, P, c_int32, c_double, c_double, c_double, c_double,
+                            c_int32]),
         "pm_stats_get": (c_int, [P, POINTER(Stats)]),
         "pm_stats_reset": (c_int, [P]),
         "pm_destroy": (None, [P]),

@@ -137,14 +137,19 @@ class PMContext:
         self._check(self.lib.pm_forward(self.ctx, _ptr(noise), _ptr(disp), _ptr(mom), _ptr(dens)))
         return disp, mom, dens
 
-    def adjoint(self, g_dens=None, g_disp=None, g_mom=None, want_filter=False):
+    def adjoint(self, g_dens=None, g_disp=None, g_mom=None, want_filter=False, g_filter_out=None):
+        """Reverse-time adjoint; g_filter_out (a [4417] tensor) receives the filter
+        gradient in place when given."""
         g_dens = self._in(g_dens, (self.ng,) * 3)
         g_disp = self._in(g_disp, (self.P, 3))
         g_mom = self._in(g_mom, (self.P, 3))
         g_noise = torch.empty((self.np,) * 3, dtype=torch.float32, device=self.device)
         g_cosmo = (c_double * 2)()
-        g_filter = (torch.empty(N_FILTER_PARAMS, dtype=torch.float32, device=self.device)
-                    if want_filter else None)
+        if g_filter_out is not None:
+            g_filter = self._in(g_filter_out, (N_FILTER_PARAMS,))
+        else:
+            g_filter = (torch.empty(N_FILTER_PARAMS, dtype=torch.float32, device=self.device)
+                        if want_filter else None)
         self._check(self.lib.pm_adjoint(self.ctx, _ptr(g_dens), _ptr(g_disp), _ptr(g_mom),
                                         _ptr(g_noise), g_cosmo, _ptr(g_filter)))
         return g_noise, (g_cosmo[0], g_cosmo[1]), g_filter
@@ -155,6 +160,30 @@ class PMContext:
         g = self._mesh() if want_grad else None
         loss = c_double(0.0)
         self._check(self.lib.pm_loss_mse(self.ctx, _ptr(dens), _ptr(target), _ptr(g), byref(loss)))
+        return loss.value, g
+
+    def loss_pk(self, dens, pk_target, n_bins=None, weight=1.0, want_grad=True):
+        """Filter-training P(k) loss (pm_loss_pk); pk_target is a host array."""
+        import numpy as np
+        dens = self._in(dens, (self.ng,) * 3)
+        n_bins = self.ng // 2 if n_bins is None else n_bins
+        pt = np.ascontiguousarray(np.asarray(pk_target, dtype=np.float64)[:n_bins])
+        if pt.shape != (n_bins,):
+            raise ValueError(f"pk_target needs {n_bins} values")
+        g = self._mesh() if want_grad else None
+        loss = c_double(0.0)
+        self._check(self.lib.pm_loss_pk(self.ctx, _ptr(dens), n_bins, pt.ctypes.data_as(c_void_p),
+                                        float(weight), byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def loss_disp(self, disp, disp_target, weight=1.0, want_grad=True):
+        """Filter-training position loss (pm_loss_disp)."""
+        disp = self._in(disp, (self.P, 3))
+        disp_target = self._in(disp_target, (self.P, 3))
+        g = self._vec() if want_grad else None
+        loss = c_double(0.0)
+        self._check(self.lib.pm_loss_disp(self.ctx, _ptr(disp), _ptr(disp_target), float(weight),
+                                          byref(loss), _ptr(g)))
         return loss.value, g
 
     def power_spectrum(self, dens, n_bins=None):
@@ -205,10 +234,16 @@ class PMContext:
         return out
 
     def adam(self, param, grad, m, v, t, lr=1e-3, betas=(0.9, 0.999), eps=1e-8):
-        for x in (param, grad, m, v):
-            self._in(x, (param.numel(),))
-        self._check(self.lib.pm_adam(self.ctx, _ptr(param), _ptr(grad), _ptr(m), _ptr(v),
-                                     param.numel(), lr, betas[0], betas[1], eps, int(t)))
+        """One Adam step on param; grad is [n] or a batch [B][n] whose mean is used."""
+        n = param.numel()
+        for x in (param, m, v):
+            self._in(x, (n,))
+        nb = grad.numel() // n
+        if grad.numel() != nb * n or nb < 1:
+            raise ValueError("grad must hold a whole number of parameter vectors")
+        self._in(grad, tuple(grad.shape))
+        self._check(self.lib.pm_adam(self.ctx, _ptr(param), _ptr(grad), nb, _ptr(m), _ptr(v),
+                                     n, lr, betas[0], betas[1], eps, int(t)))
 
     def reset_stats(self):
         self._check(self.lib.pm_stats_reset(self.ctx))

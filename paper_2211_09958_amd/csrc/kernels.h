@@ -196,6 +196,11 @@ void launch_mse(const float* d, const float* t, float* g, long n3, double* parti
 // P(k) shells from a full half spectrum [n][n][cs]: bins[3*b + {0,1,2}] +=
 // {w |d_k|^2, w |n|, w} for b = round(|n|) in [1, nbins].
 void launch_pk_bin(const float2* spec, int n, int cs, int nbins, double* bins, hipStream_t s);
+// spec[k] *= table[|n|^2] over the half spectrum
+void launch_radial_scale(float2* spec, int n, int cs, const float* table, hipStream_t s);
+// block partials of Sum (minimum-image a - b)^2; g = gscale * (a - b) wrapped (nullable)
+void launch_mse_periodic(const float* a, const float* b, float* g, long n, float box, float gscale,
+                         double* partials, int nblocks, hipStream_t s);
 
 // Filter network (2-64-64-1 SiLU): radial[n2] = (1 + g(|k|/kNyq, a)) * base(n2)
 // with base(n2) = fscale / n2 (0 at n2 = 0); also table (nullable) = 1 + g.
@@ -205,8 +210,9 @@ void launch_mlp_table(const float* theta, int n, float box, float a, float fscal
 void launch_mlp_backward(const float* theta, int n, float box, float a, const float* fbar,
                          float* gtheta, float* scratch, long scratch_elems, hipStream_t s);
 long mlp_backward_scratch(int n);
-void launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1,
-                 float b2, float eps, float bc1, float bc2, hipStream_t s);
+// Adam step on the mean of ngrad gradients g[ngrad][n]
+void launch_adam(float* p, const float* g, int ngrad, float* m, float* v, int n, float lr,
+                 float b1, float b2, float eps, float bc1, float bc2, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 
 }  // namespace pmx

@@ -147,12 +147,14 @@ k_mlp_reduce(const float* __restrict__ scratch, int nblocks, float* __restrict__
 }
 
 __global__ void __launch_bounds__(256)
-k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+k_adam(float* __restrict__ p, const float* __restrict__ g, int ngrad, float* __restrict__ m,
        float* __restrict__ v, int n, float lr, float b1, float b2, float eps, float bc1,
        float bc2) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    const float gi = g[i];
+    float gi = 0.f;  // mean of the batch of gradients, summed in a fixed order
+    for (int j = 0; j < ngrad; ++j) gi += g[(long)j * n + i];
+    gi /= (float)ngrad;
     const float mi = b1 * m[i] + (1.f - b1) * gi;
     const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
     m[i] = mi;
@@ -184,10 +186,10 @@ void launch_mlp_backward(const float* theta, int n, float, float a, const float*
                        gtheta);
 }
 
-void launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1,
-                 float b2, float eps, float bc1, float bc2, hipStream_t s) {
-    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2,
-                       eps, bc1, bc2);
+void launch_adam(float* p, const float* g, int ngrad, float* m, float* v, int n, float lr,
+                 float b1, float b2, float eps, float bc1, float bc2, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, p, g, ngrad, m, v, n, lr,
+                       b1, b2, eps, bc1, bc2);
 }
 
 }  // namespace pmx

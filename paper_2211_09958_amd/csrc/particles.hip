@@ -795,6 +795,40 @@ k_pk_bin(const float2* __restrict__ spec, int n, int cs, int nbins, double* __re
         if (sb[i] != 0.0) atomicAdd(&bins[i], sb[i]);
 }
 
+// Multiplies every half-spectrum mode by table[|n|^2] (a radial cotangent).
+__global__ void __launch_bounds__(kBlock)
+k_radial_scale(float2* __restrict__ spec, int n, int cs, const float* __restrict__ table) {
+    const int h = n / 2 + 1;
+    const long N = (long)n * n * h;
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < N; i += (long)gridDim.x * kBlock) {
+        const int k2 = (int)(i % h);
+        const long row = i / h;
+        const int i1 = (int)(row % n), i0 = (int)(row / n);
+        const int n0 = i0 < n / 2 ? i0 : i0 - n, n1 = i1 < n / 2 ? i1 : i1 - n;
+        const float t = table[n0 * n0 + n1 * n1 + k2 * k2];
+        float2 d = spec[row * cs + k2];
+        d.x *= t;
+        d.y *= t;
+        spec[row * cs + k2] = d;
+    }
+}
+
+// Periodic squared separation of two displacement arrays (minimum image, wrap
+// d - box*floor(d/box + 1/2)); block partials of Sum d^2 and g = gscale * d.
+__global__ void __launch_bounds__(kBlock)
+k_mse_periodic(const float* __restrict__ a, const float* __restrict__ b, float* __restrict__ g,
+               long n, float box, float inv_box, float gscale, double* partials) {
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+        float d = a[i] - b[i];
+        d -= box * floorf(d * inv_box + 0.5f);
+        acc += (double)d * d;
+        if (g) g[i] = gscale * d;
+    }
+    double s = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
 __global__ void __launch_bounds__(kBlock) k_zero(uint32_t* __restrict__ p, long n) {
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) p[i] = 0u;
 }
@@ -1052,6 +1086,17 @@ void launch_mse(const float* d, const float* t, float* g, long n3, double* parti
                 int nblocks, hipStream_t s) {
     hipLaunchKernelGGL(k_mse, dim3(nblocks), dim3(kBlock), 0, s, d, t, g, n3, (float)(2.0 / n3),
                        partials);
+}
+
+void launch_radial_scale(float2* spec, int n, int cs, const float* table, hipStream_t s) {
+    const long N = (long)n * n * (n / 2 + 1);
+    hipLaunchKernelGGL(k_radial_scale, dim3(grid_for(N)), dim3(kBlock), 0, s, spec, n, cs, table);
+}
+
+void launch_mse_periodic(const float* a, const float* b, float* g, long n, float box, float gscale,
+                         double* partials, int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_mse_periodic, dim3(nblocks), dim3(kBlock), 0, s, a, b, g, n, box,
+                       1.f / box, gscale, partials);
 }
 
 void launch_pk_bin(const float2* spec, int n, int cs, int nbins, double* bins, hipStream_t s) {

@@ -89,7 +89,8 @@ struct Plan {
     size_t cplx, disp, mom, xi, pi, disp2, mom2, xi2, pi2, id, id2, fin_disp, fin_mom, s_ic, tmpv,
         noise, ckpt;
     size_t counts, offsets, keys, ranks, scan_tmp;
-    size_t radial_f, radial_ic, radial_ic_dom, tw, tw_stages, partials, sums, maxbits, pkbins;
+    size_t radial_f, radial_ic, radial_ic_dom, losstab, tw, tw_stages, partials, sums, maxbits,
+        pkbins;
     size_t theta, gtheta, fbar, mlp_scratch;
     long cplx_elems, P, nkeys, ntab_f, ntab_p;
     int cs, cs_p, tile, nt, nckpt;
@@ -137,6 +138,7 @@ struct Plan {
         radial_f = take(ntab_f * sizeof(float));
         radial_ic = take(ntab_p * sizeof(float));
         radial_ic_dom = take(ntab_p * sizeof(float));
+        losstab = take(ntab_f * sizeof(float));
         tw = take((size_t)ng * sizeof(float2));
         tw_stages = take(kStageTableSize * sizeof(float2));
         // FP64 block partials: one per 256-particle block, three sets for the IC check
@@ -175,6 +177,8 @@ struct pm_ctx {
     int32_t* fin_p;
     float *s_ic, *tmpv, *noise;
     float *radial_f, *radial_ic, *radial_ic_dom, *theta, *gtheta, *fbar, *mlp_scratch;
+    float* losstab;                    // radial cotangent table of pm_loss_pk
+    std::vector<float> losstab_host;   // its host copy (kept alive across the async upload)
     float2* tw;
     float2* tw_stages;
     Twiddles twd;
@@ -546,6 +550,7 @@ int pm_init(const pm_config* cfg, const pm_cosmology* cosmo, void* workspace, si
     ctx->radial_f = ctx->at<float>(p.radial_f);
     ctx->radial_ic = ctx->at<float>(p.radial_ic);
     ctx->radial_ic_dom = ctx->at<float>(p.radial_ic_dom);
+    ctx->losstab = ctx->at<float>(p.losstab);
     ctx->tw = ctx->at<float2>(p.tw);
     ctx->tw_stages = ctx->at<float2>(p.tw_stages);
     ctx->twd = Twiddles{ctx->tw, ctx->ng, ctx->tw_stages};
@@ -855,6 +860,83 @@ int pm_loss_mse(pm_ctx* ctx, const float* dens, const float* target, float* g_de
     return PM_OK;
 }
 
+int pm_loss_pk(pm_ctx* ctx, const float* dens, int32_t n_bins, const double* pk_target,
+               double weight, double* loss, float* g_dens) {
+    PM_TRY(ctx_check(ctx));
+    if (!dens || !pk_target) return ctx->fail(PM_EINVAL, "dens and pk_target are required");
+    if (n_bins < 1 || n_bins > ctx->ng) return ctx->fail(PM_EINVAL, "n_bins must be in [1, mesh]");
+    if (!std::isfinite(weight)) return ctx->fail(PM_EINVAL, "weight must be finite");
+    hipStream_t s = ctx->stream;
+    const int ng = ctx->ng;
+    launch_to_pitched(dens, ctx->creal(0), ng, ctx->lat.rp, 1.f, s);
+    launch_fft3_r2c(ctx->C[0], ng, ctx->cs, 1, ctx->plan.cplx_elems, ctx->twd, s);
+    launch_zero(ctx->pkbins, 3 * (size_t)n_bins * sizeof(double), s);
+    launch_pk_bin(ctx->C[0], ng, ctx->cs, n_bins, ctx->pkbins, s);
+    PM_TRY(ctx->hip_check("pm_loss_pk"));
+    std::vector<double> h(3 * (size_t)n_bins);
+    if (hipMemcpyAsync(h.data(), ctx->pkbins, h.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return ctx->fail(PM_EHIP, "reading P(k) failed");
+    // P_b = L^3 / Ng^6 * <|delta_k|^2>_b; L = w * mean_b (P_b / T_b - 1)^2 over the
+    // shells holding modes and a nonzero target
+    const double L = ctx->cfg.box, n6 = std::pow((double)ng, 6.0), L3 = L * L * L;
+    std::vector<double> gP(n_bins, 0.0);
+    int used = 0;
+    for (int b = 0; b < n_bins; ++b)
+        if (h[3 * b + 2] > 0 && pk_target[b] != 0.0 && std::isfinite(pk_target[b])) ++used;
+    if (used == 0) return ctx->fail(PM_EINVAL, "no shell has both modes and a nonzero target");
+    double acc = 0.0;
+    for (int b = 0; b < n_bins; ++b) {
+        const double cnt = h[3 * b + 2];
+        if (!(cnt > 0 && pk_target[b] != 0.0 && std::isfinite(pk_target[b]))) continue;
+        const double r = h[3 * b] / cnt * L3 / n6 / pk_target[b] - 1.0;
+        acc += r * r;
+        gP[b] = weight * 2.0 * r / (pk_target[b] * used);
+    }
+    if (loss) *loss = weight * acc / used;
+    if (!std::isfinite(acc)) return ctx->fail(PM_ENUMERIC, "non-finite P(k) loss");
+    if (!g_dens) return PM_OK;
+    // d L / d delta(x) = 2 Sum_k t_k delta_k e^{ik.x} (unnormalised inverse DFT of the
+    // half spectrum) with t_k = dL/dP_b L^3 / (Ng^6 N_b): a radial table in |n|^2
+    const long ntab = ctx->plan.ntab_f;
+    ctx->losstab_host.assign(ntab, 0.f);
+    for (long q = 1; q < ntab; ++q) {
+        const int b = (int)std::floor(std::sqrt((double)q) + 0.5);
+        if (b < 1 || b > n_bins || gP[b - 1] == 0.0) continue;
+        ctx->losstab_host[q] = (float)(2.0 * gP[b - 1] * L3 / (n6 * h[3 * (b - 1) + 2]));
+    }
+    if (hipMemcpyAsync(ctx->losstab, ctx->losstab_host.data(), ntab * sizeof(float),
+                       hipMemcpyHostToDevice, s) != hipSuccess)
+        return ctx->fail(PM_EHIP, "upload of the loss table failed");
+    launch_radial_scale(ctx->C[0], ng, ctx->cs, ctx->losstab, s);
+    launch_fft3_c2r(ctx->C[0], ng, ctx->cs, 1, ctx->plan.cplx_elems, ctx->twd, s);
+    launch_from_pitched(ctx->creal(0), g_dens, ng, ctx->lat.rp, s);
+    return ctx->hip_check("pm_loss_pk");
+}
+
+int pm_loss_disp(pm_ctx* ctx, const float* disp, const float* disp_target, double weight,
+                 double* loss, float* g_disp) {
+    PM_TRY(ctx_check(ctx));
+    if (!disp || !disp_target) return ctx->fail(PM_EINVAL, "disp and disp_target are required");
+    if (!std::isfinite(weight)) return ctx->fail(PM_EINVAL, "weight must be finite");
+    const long n = 3 * ctx->P;
+    const double cell = ctx->cfg.box / ctx->ng;
+    const double norm = weight / ((double)ctx->P * cell * cell);
+    const int nb = std::min(particle_blocks(n), 4096);
+    launch_mse_periodic(disp, disp_target, g_disp, n, (float)ctx->cfg.box, (float)(2.0 * norm),
+                        ctx->partials, nb, ctx->stream);
+    PM_TRY(ctx->hip_check("pm_loss_disp"));
+    if (loss) {
+        launch_reduce(ctx->partials, nb, ctx->pkbins, 0, ctx->stream);
+        double v = 0.0;
+        if (hipMemcpyAsync(&v, ctx->pkbins, sizeof(double), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+            hipStreamSynchronize(ctx->stream) != hipSuccess)
+            return ctx->fail(PM_EHIP, "reading loss failed");
+        *loss = norm * v;
+    }
+    return PM_OK;
+}
+
 int pm_power_spectrum(pm_ctx* ctx, const float* dens, int32_t n_bins, double* k_out,
                       double* pk_out, double* nmodes_out) {
     PM_TRY(ctx_check(ctx));
@@ -957,12 +1039,13 @@ int pm_filter_table(pm_ctx* ctx, double a, float* table) {
     return ctx->hip_check("pm_filter_table");
 }
 
-int pm_adam(pm_ctx* ctx, float* param, const float* grad, float* m, float* v, int32_t n,
-            double lr, double beta1, double beta2, double eps, int32_t t) {
+int pm_adam(pm_ctx* ctx, float* param, const float* grad, int32_t n_grads, float* m, float* v,
+            int32_t n, double lr, double beta1, double beta2, double eps, int32_t t) {
     PM_TRY(ctx_check(ctx));
-    if (!param || !grad || !m || !v || n < 1 || t < 1) return ctx->fail(PM_EINVAL, "bad Adam arguments");
+    if (!param || !grad || !m || !v || n < 1 || t < 1 || n_grads < 1)
+        return ctx->fail(PM_EINVAL, "bad Adam arguments");
     const double bc1 = 1.0 - std::pow(beta1, t), bc2 = 1.0 - std::pow(beta2, t);
-    launch_adam(param, grad, m, v, n, (float)lr, (float)beta1, (float)beta2, (float)eps,
+    launch_adam(param, grad, n_grads, m, v, n, (float)lr, (float)beta1, (float)beta2, (float)eps,
                 (float)bc1, (float)bc2, ctx->stream);
     return ctx->hip_check("pm_adam");
 }

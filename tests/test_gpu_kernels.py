@@ -129,3 +129,48 @@ def test_loss_mse():
     ref = np.mean((a.astype(np.float64) - b) ** 2)
     assert abs(L / ref - 1) < 1e-6
     np.testing.assert_allclose(host(g), 2 * (a.astype(np.float64) - b) / a.size, rtol=1e-5, atol=1e-12)
+
+
+@pytest.mark.parametrize("n_bins", [32, 56, 64])
+def test_loss_pk_matches_oracle(n_bins):
+    """P(k) training loss and its mesh cotangent; 56 and 64 include empty corner
+    shells (round(|n|) > 55 holds no mode of a 64^3 mesh)."""
+    pm = context(32, 64, 64.0, 1)
+    # a clustered field: CIC density of displaced lattice particles
+    q = (np.indices((32,) * 3).reshape(3, -1).T + 0.5) * 2.0
+    d = M.density(q + normal((32 ** 3, 3), 60) * 2.5, 64, 64.0, 32 ** 3)
+    t = M.density(q + normal((32 ** 3, 3), 61) * 2.0, 64, 64.0, 32 ** 3)
+    pt = M.power_spectrum(t, 64.0, n_bins)[1]
+    pt = np.where(np.isfinite(pt), pt, 0.0)
+    L_ref, g_ref = opm.pk_loss(d, pt, 64.0, n_bins, weight=0.3)
+    L, g = pm.loss_pk(dev(d), pt, n_bins, weight=0.3)
+    assert abs(L / L_ref - 1) < 1e-5
+    assert rel_l2(host(g), g_ref) < 1e-5
+
+
+def test_loss_pk_skips_zero_targets_and_rejects_empty():
+    pm = context(8, 16, 16.0, 1)
+    d = normal((16,) * 3, 62)
+    pt = M.power_spectrum(normal((16,) * 3, 63), 16.0, 8)[1]
+    pt[[0, 3]] = 0.0                      # shells without a target are left out
+    L_ref, g_ref = opm.pk_loss(d, pt, 16.0, 8)
+    L, g = pm.loss_pk(dev(d), pt, 8)
+    assert abs(L / L_ref - 1) < 1e-5
+    assert rel_l2(host(g), g_ref) < 1e-5
+    with pytest.raises(Exception, match="PM_EINVAL"):
+        pm.loss_pk(dev(d), np.zeros(8), 8)
+
+
+def test_loss_disp_matches_oracle_with_wrap():
+    pm = context(16, 32, 32.0, 1)
+    P = 16 ** 3
+    s = uniform((P, 3), 64, -3.0, 3.0)
+    shifts = np.round(uniform((P, 3), 65, -1.0, 1.0)) * 32.0
+    t = s + normal((P, 3), 66) * 0.5 + shifts
+    t[:10, 0] = s[:10, 0] + 15.9             # separations near half a box
+    t[10:20, 1] = s[10:20, 1] - 16.1
+    s32, t32 = s.astype(np.float32), t.astype(np.float32)
+    L_ref, g_ref = opm.disp_loss(s32, t32, 32.0, 32, weight=0.01)
+    L, g = pm.loss_disp(dev(s32), dev(t32), weight=0.01)
+    assert abs(L / L_ref - 1) < 1e-5
+    assert rel_l2(host(g), g_ref) < 1e-5
