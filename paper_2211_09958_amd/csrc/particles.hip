@@ -89,17 +89,34 @@ __device__ __forceinline__ uint32_t drift_units(float coeff, int32_t pq, const L
     return (uint32_t)__float2ll_rn(d);
 }
 
+// Sum over a work-group of NTH threads; the total is valid in thread 0.
+template <int NTH = kBlock>
 __device__ __forceinline__ double block_sum(double v) {
-    __shared__ double red[kBlock / 64];
+    __shared__ double red[NTH / 64];
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) red[wid] = v;
     __syncthreads();
     double s = 0.0;
     if (threadIdx.x == 0)
-        for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+        for (int w = 0; w < NTH / 64; ++w) s += red[w];
     __syncthreads();
     return s;
+}
+
+// Max of a non-negative float over the block, as float bits atomically folded
+// into *out by one lane per block (non-negative floats order like their bits).
+__device__ __forceinline__ void block_max_to(float m, unsigned* out) {
+    __shared__ float red[kBlock / 64];
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_down(m, o));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) m = fmaxf(m, red[w]);
+        atomicMax(out, __float_as_uint(m));
+    }
+    __syncthreads();
 }
 
 // ------------------------------------------------------------- binning
@@ -371,8 +388,7 @@ k_absmax(const float* __restrict__ v, long n, unsigned* __restrict__ out) {
     float m = 0.f;
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock)
         m = fmaxf(m, fabsf(v[i]));
-    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_down(m, o));
-    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+    block_max_to(m, out);
 }
 
 // ------------------------------------------------------------- gathers
@@ -405,9 +421,15 @@ struct GatherArgs {
     double* partials;     // one per tile (nullable)
 };
 
+// Threads per gather work-group: the three-mesh tile takes 59 KB of LDS (two
+// work-groups per CU), so those modes use larger work-groups to keep more waves
+// in flight.
+constexpr int gather_threads(int mode) { return mode == kWgrad ? kBlock : 2 * kBlock; }
+
 template <int T, int MODE>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(gather_threads(MODE))
 k_gather_tile(GatherArgs A, Lattice L, int nt, const uint32_t* __restrict__ offsets) {
+    constexpr int NTH = gather_threads(MODE);
     constexpr int NM = MODE == kWgrad ? 1 : 3;
     constexpr int TH = T + 1, TH3 = TH * TH * TH;
     __shared__ float mf[NM * TH3];
@@ -418,7 +440,7 @@ k_gather_tile(GatherArgs A, Lattice L, int nt, const uint32_t* __restrict__ offs
     const int mask = L.ng - 1;
     double acc = 0.0;
     if (pbeg < pend) {   // uniform across the work-group
-        for (int c = threadIdx.x; c < TH3; c += kBlock) {
+        for (int c = threadIdx.x; c < TH3; c += NTH) {
             const int l2 = c % TH, l1 = (c / TH) % TH, l0 = c / (TH * TH);
             const long g = ((long)((lo[0] + l0) & mask) * L.ng + ((lo[1] + l1) & mask)) * A.pitch +
                            ((lo[2] + l2) & mask);
@@ -427,7 +449,7 @@ k_gather_tile(GatherArgs A, Lattice L, int nt, const uint32_t* __restrict__ offs
         }
         __syncthreads();
         const float ic = L.inv_cell;
-        for (uint32_t p = pbeg + threadIdx.x; p < pend; p += kBlock) {
+        for (uint32_t p = pbeg + threadIdx.x; p < pend; p += NTH) {
             uint32_t x[3] = {A.xq[3 * p], A.xq[3 * p + 1], A.xq[3 * p + 2]};
             int ii[3];
             float t[3];
@@ -507,7 +529,7 @@ k_gather_tile(GatherArgs A, Lattice L, int nt, const uint32_t* __restrict__ offs
         }
     }
     if (A.partials) {
-        const double s = block_sum(acc);
+        const double s = block_sum<NTH>(acc);
         if (threadIdx.x == 0) A.partials[tile] = s;
     }
 }
@@ -629,8 +651,7 @@ k_recon_err(const uint32_t* __restrict__ a, const uint32_t* __restrict__ id,
     }
     double s = block_sum(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
-    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_down(mx, o));
-    if ((threadIdx.x & 63) == 0) atomicMax(maxbits, __float_as_uint(mx));
+    block_max_to(mx, maxbits);
 }
 
 // x = q + D0 s, p = G0 s in fixed point for lattice particle p.
@@ -705,8 +726,7 @@ k_ic_check(const float* __restrict__ sm, long sStride, long rp, float D0, float 
         partials[gridDim.x + blockIdx.x] = s1;
         partials[2 * gridDim.x + blockIdx.x] = s2;
     }
-    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_down(mx, o));
-    if ((threadIdx.x & 63) == 0) atomicMax(maxbits, __float_as_uint(mx));
+    block_max_to(mx, maxbits);
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -914,15 +934,15 @@ static void gather_dispatch(const GatherArgs& A, const Lattice& L, const Bins& b
     const unsigned ntiles = (unsigned)b.nt * b.nt * b.nt;
     switch (b.tile) {
         case 4:
-            hipLaunchKernelGGL((k_gather_tile<4, MODE>), dim3(ntiles), dim3(kBlock), 0, s, A, L, b.nt,
+            hipLaunchKernelGGL((k_gather_tile<4, MODE>), dim3(ntiles), dim3(gather_threads(MODE)), 0, s, A, L, b.nt,
                                b.offsets);
             break;
         case 8:
-            hipLaunchKernelGGL((k_gather_tile<8, MODE>), dim3(ntiles), dim3(kBlock), 0, s, A, L, b.nt,
+            hipLaunchKernelGGL((k_gather_tile<8, MODE>), dim3(ntiles), dim3(gather_threads(MODE)), 0, s, A, L, b.nt,
                                b.offsets);
             break;
         default:
-            hipLaunchKernelGGL((k_gather_tile<16, MODE>), dim3(ntiles), dim3(kBlock), 0, s, A, L,
+            hipLaunchKernelGGL((k_gather_tile<16, MODE>), dim3(ntiles), dim3(gather_threads(MODE)), 0, s, A, L,
                                b.nt, b.offsets);
             break;
     }

@@ -693,7 +693,8 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
     const int N = c.n_steps;
     const long P = ctx->P;
     const size_t vec = (size_t)P * 3 * sizeof(float);
-    const int nb = particle_blocks(P);
+    // grid-stride reductions over the particles: block partials + one max per block
+    const int nb = std::min(particle_blocks(P), 4096);
     const int slotS = 0, slotD = N + 1, slotX = 2 * N + 1;   // S_m, D_n, extras
     const int xD0 = slotX, xG0 = slotX + 1, xSig = slotX + 2, xOm = slotX + 3,
               xIc = slotX + 4, xIcMom = slotX + 5, xIcMomRef = slotX + 6, xCk = slotX + 8;

@@ -11,8 +11,9 @@ from synthetic import normal, uniform
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("ng", [8, 16, 32, 64, 128, 256])
-def test_fft_r2c_matches_oracle(ng):
+@pytest.mark.parametrize("ng", [8, 16, 32, 64, 128, 256, 512])
+def test_fft_r2c_matches_oracle(ng, monkeypatch):
+    monkeypatch.setattr(M, "WORKERS", 16)
     pm = context(8, ng, float(ng), 1)
     x = normal((ng,) * 3, 100 + ng).astype(np.float32)
     got = pm.fft_r2c(dev(x)).cpu().numpy().astype(np.complex128)

@@ -247,3 +247,25 @@ def test_filter_training_reduces_loss():
     assert rep["adam_steps"] == 48
     total = [e["loss_pk"] + e["loss_disp"] for e in h]
     assert total[-1] < 0.75 * total[0] and total[-1] < total[len(total) // 2]
+
+
+def test_trained_filter_beats_plain_on_heldout_seeds():
+    """The committed filter (trained by train_filter on seeds 0..55 at 128^3
+    particles, 128^3 vs 512^3 meshes, box 128, 31 steps) against plain PM on two
+    held-out seeds: P(k) of the final density against the 512^3-mesh run of the
+    same seed, both on the 128^3 mesh, max over shells k <= k_Nyq/2."""
+    import os
+    here = os.path.dirname(os.path.abspath(api.__file__))
+    theta = np.load(os.path.join(here, "weights", "filter_128p_128m_to_512m.npy"))
+    fine = context(128, 512, 128.0, 31)
+    coarse = context(128, 128, 128.0, 31, filter=True)
+    errs = {"plain": [], "learned": []}
+    for seed in (56, 63):
+        n = dev(white_noise(128, seed))
+        ref = coarse.power_spectrum(coarse.density(fine.forward(n, want_density=False)[0]), 32)[1]
+        for name, w in (("plain", mlp_init(0)), ("learned", theta)):
+            coarse.set_filter(dev(w))
+            pk = coarse.power_spectrum(coarse.forward(n)[2], 32)[1]
+            errs[name].append(np.max(np.abs(pk / ref - 1)))
+    print({k: np.round(v, 4) for k, v in errs.items()})
+    assert np.mean(errs["learned"]) < 0.6 * np.mean(errs["plain"])
