@@ -8,7 +8,9 @@
 //         X[k] = (Z[k] + Z*[n/2-k]) / 2 - i W^k (Z[k] - Z*[n/2-k]) / 2;
 //   * axes 1 and 0 (strided): a work-group loads an n x W tile (W consecutive
 //     columns, each row segment W*8 bytes) and transforms the W columns
-//     together, exchanging through LDS between Stockham stages.
+//     together, exchanging through LDS between Stockham stages.  Rows are
+//     stored in the blocked order of layout.h, which keeps both strided passes
+//     within a few dozen pages.
 // The Poisson multiply F~_j = i k_j f(|k|) delta_k / k^2 is fused into the
 // axis-0 pass: one load of the spectrum, one forward column FFT, then for each
 // j a multiply and inverse column FFT straight to the output buffer, so the
@@ -18,6 +20,7 @@
 
 #include "fft_engine.h"
 #include "kernels.h"
+#include "layout.h"
 #include "xcd.h"
 
 namespace pmx {
@@ -113,10 +116,12 @@ k_fft_x_c2r(float2* __restrict__ buf, int cs, long nrows, long bufStride,
 
 // ---------------------------------------------------------- strided axes
 
-// Tile t -> (a, cb): column base a*A + cb*W, element p at + p*S.
-template <int H, int DIR>
+// Tile t -> (a, cb): columns cb*W .. cb*W+W-1 of the rows with the other slow
+// index fixed to a; element p of the transform sits in mesh row (a, p) for
+// AXIS = 1 and (p, a) for AXIS = 0 (storage order: layout.h).
+template <int H, int DIR, int AXIS>
 __global__ void __launch_bounds__(Cfg<H>::T * Cfg<H>::W, Cfg<H>::MINW)
-k_fft_strided(float2* __restrict__ buf, long S, long A, int ncb, long bufStride,
+k_fft_strided(float2* __restrict__ buf, int cs, int ncb, long bufStride,
               const float2* __restrict__ tw, int ntw,
             const float2* __restrict__ st) {
     constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::W;
@@ -124,14 +129,17 @@ k_fft_strided(float2* __restrict__ buf, long S, long A, int ncb, long bufStride,
     const int c = threadIdx.x % W, j = threadIdx.x / W;
     const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
     const int a = tile / ncb, cb = tile % ncb;
-    float2* base = buf + blockIdx.y * bufStride + a * A + cb * W + c;
+    float2* base = buf + blockIdx.y * bufStride + cb * W + c;
+    auto at = [&](int p) -> float2& {
+        return base[(AXIS == 1 ? mesh_row(a, p, H) : mesh_row(p, a, H)) * cs];
+    };
     float2 v[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = base[(j + e * T) * S];
+    for (int e = 0; e < E; ++e) v[e] = at(j + e * T);
     fft_lds<H, E, DIR>(v, lds, W, c, j, st);
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) base[(j + e * T) * S] = lds[lpad(j + e * T) * W + c];
+    for (int e = 0; e < E; ++e) at(j + e * T) = lds[lpad(j + e * T) * W + c];
 }
 
 __device__ __forceinline__ int signed_freq(int p, int n) { return p < n / 2 ? p : p - n; }
@@ -151,11 +159,11 @@ k_grad_z(const float2* __restrict__ src, float2* __restrict__ dst, long dstStrid
     const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
     const int i1 = tile / ncb, cb = tile % ncb;
     const int k2 = cb * W + c;
-    const long S = (long)n * cs;
-    const long col = (long)i1 * cs + k2;
+    // element p of the column (mesh row (p, i1), column k2)
+    auto off = [&](int p) -> long { return mesh_row(p, i1, n) * cs + k2; };
     float2 v[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = src[col + (j + e * T) * S];
+    for (int e = 0; e < E; ++e) v[e] = src[off(j + e * T)];
     fft_lds<H, E, -1>(v, lds, W, c, j, st);
     __syncthreads();
     const int n1 = signed_freq(i1, n);
@@ -178,13 +186,14 @@ k_grad_z(const float2* __restrict__ src, float2* __restrict__ dst, long dstStrid
         // i n_j g for j = 1, 2 (zero on the Nyquist plane of the axis)
         const float f1 = n1 == -n / 2 ? 0.f : (float)n1;
         const float f2 = k2 == n / 2 ? 0.f : (float)k2;
-        float2* o1 = dst + dstStride + col;
-        float2* o2 = dst + 2 * dstStride + col;
+        float2* o1 = dst + dstStride;
+        float2* o2 = dst + 2 * dstStride;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const float2 g = lds[lpad(j + e * T) * W + c];
-            o1[(j + e * T) * S] = make_float2(-g.y * f1, g.x * f1);
-            o2[(j + e * T) * S] = make_float2(-g.y * f2, g.x * f2);
+            const long o = off(j + e * T);
+            o1[o] = make_float2(-g.y * f1, g.x * f1);
+            o2[o] = make_float2(-g.y * f2, g.x * f2);
         }
     }
 #pragma unroll
@@ -196,9 +205,8 @@ k_grad_z(const float2* __restrict__ src, float2* __restrict__ dst, long dstStrid
     __syncthreads();
     fft_lds<H, E, 1>(v, lds, W, c, j, st);
     __syncthreads();
-    float2* o0 = dst + col;
 #pragma unroll
-    for (int e = 0; e < E; ++e) o0[(j + e * T) * S] = lds[lpad(j + e * T) * W + c];
+    for (int e = 0; e < E; ++e) dst[off(j + e * T)] = lds[lpad(j + e * T) * W + c];
 }
 
 // Axis-0 pass of the transposed gradient operator (see launch_grad_adj_z).
@@ -217,8 +225,8 @@ k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
     const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
     const int i1 = tile / ncb, cb = tile % ncb;
     const int k2 = cb * W + c;
-    const long S = (long)n * cs;
-    const long col = (long)i1 * cs + k2;
+    // element p of the column (mesh row (p, i1), column k2)
+    auto off = [&](int p) -> long { return mesh_row(p, i1, n) * cs + k2; };
     const int n1 = signed_freq(i1, n);
     const bool in_half = k2 <= n / 2;
     const float f1 = n1 == -n / 2 ? 0.f : (float)n1;
@@ -226,7 +234,7 @@ k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
     float2 v[E], a[E];
     // forward FFT of G_0, kept as n0 G_0 (zero on its Nyquist plane)
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = src[col + (j + e * T) * S];
+    for (int e = 0; e < E; ++e) v[e] = src[off(j + e * T)];
     fft_lds<H, E, -1>(v, lds, W, c, j, st);
     __syncthreads();
 #pragma unroll
@@ -238,11 +246,12 @@ k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
     }
     // forward FFT of n1 G_1 + n2 G_2, added
     {
-        const float2* g1 = src + srcStride + col;
-        const float2* g2 = src + 2 * srcStride + col;
+        const float2* g1 = src + srcStride;
+        const float2* g2 = src + 2 * srcStride;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const float2 x = g1[(j + e * T) * S], y = g2[(j + e * T) * S];
+            const long o = off(j + e * T);
+            const float2 x = g1[o], y = g2[o];
             v[e] = make_float2(f1 * x.x + f2 * y.x, f1 * x.y + f2 * y.y);
         }
     }
@@ -258,7 +267,7 @@ k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
     if constexpr (FILT) {
         // dL/df(|n|^2) += mult Re(conj(Sum_j n_j G_j) i fscale/|n|^2 dens_k)
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = dens[col + (j + e * T) * S];
+        for (int e = 0; e < E; ++e) v[e] = dens[off(j + e * T)];
         __syncthreads();
         fft_lds<H, E, -1>(v, lds, W, c, j, st);
         __syncthreads();
@@ -287,9 +296,8 @@ k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
     __syncthreads();
     fft_lds<H, E, 1>(v, lds, W, c, j, st);
     __syncthreads();
-    float2* out = dst + col;
 #pragma unroll
-    for (int e = 0; e < E; ++e) out[(j + e * T) * S] = lds[lpad(j + e * T) * W + c];
+    for (int e = 0; e < E; ++e) dst[off(j + e * T)] = lds[lpad(j + e * T) * W + c];
 }
 
 // Calls f(std::integral_constant<int, n>) for the supported power-of-two sizes.
@@ -330,13 +338,15 @@ template <int N>
 void strided(float2* buf, int cs, int axis, int dir, int nbuf, long bufStride, const Twiddles& tw, hipStream_t s) {
     constexpr int W = Cfg<N>::W, T = Cfg<N>::T;
     int ncb = cs / W;
-    long S = axis == 1 ? cs : (long)N * cs;
-    long A = axis == 1 ? (long)N * cs : cs;
-    dim3 grid(N * ncb, nbuf);
-    if (dir < 0)
-        hipLaunchKernelGGL((k_fft_strided<N, -1>), grid, dim3(T * W), 0, s, buf, S, A, ncb, bufStride, tw.w, tw.n, tw.stages);
+    dim3 grid(N * ncb, nbuf), block(T * W);
+    if (axis == 1 && dir < 0)
+        hipLaunchKernelGGL((k_fft_strided<N, -1, 1>), grid, block, 0, s, buf, cs, ncb, bufStride, tw.w, tw.n, tw.stages);
+    else if (axis == 1)
+        hipLaunchKernelGGL((k_fft_strided<N, 1, 1>), grid, block, 0, s, buf, cs, ncb, bufStride, tw.w, tw.n, tw.stages);
+    else if (dir < 0)
+        hipLaunchKernelGGL((k_fft_strided<N, -1, 0>), grid, block, 0, s, buf, cs, ncb, bufStride, tw.w, tw.n, tw.stages);
     else
-        hipLaunchKernelGGL((k_fft_strided<N, 1>), grid, dim3(T * W), 0, s, buf, S, A, ncb, bufStride, tw.w, tw.n, tw.stages);
+        hipLaunchKernelGGL((k_fft_strided<N, 1, 0>), grid, block, 0, s, buf, cs, ncb, bufStride, tw.w, tw.n, tw.stages);
 }
 
 }  // namespace

@@ -131,12 +131,13 @@ void launch_gather_force(const uint32_t* xq, const uint32_t* id, const float* fm
 void launch_unkick_vjp(const uint32_t* xq, int32_t* pq, const float* fmesh, long fStride,
                        const Lattice& L, const Bins& b, float coeff, const float* pi, float* xi,
                        double* partials, hipStream_t s);
-// xi += g_scale Sum grad w . mesh (mesh row pitch given).  mode 1 also does the
-// rest of a reverse step: partials Sum xi . p, pi += drift xi, x -= drift p
-// (exact inverse of the forward drift); mode 2 only updates xi.
+// xi += g_scale Sum grad w . mesh (mesh row pitch given; rows in the workspace
+// order of layout.h, or in plain order when dense).  mode 1 also does the rest
+// of a reverse step: partials Sum xi . p, pi += drift xi, x -= drift p (exact
+// inverse of the forward drift); mode 2 only updates xi.
 void launch_wgrad(const float* mesh, long pitch, float g_scale, uint32_t* xq, const int32_t* pq,
                   float* xi, float* pi, const Lattice& L, const Bins& b, float drift, int mode,
-                  double* partials, hipStream_t s);
+                  double* partials, hipStream_t s, bool dense = false);
 // Displacements (float, Mpc/h, lattice order) -> fixed-point positions q + s
 // in lattice order, id = identity.
 void launch_to_fixed(const float* disp, uint32_t* xq, uint32_t* id, const Lattice& L,
@@ -180,6 +181,8 @@ void launch_ic_check(const float* smesh, long sStride, long rp, float D0, float 
 void launch_to_pitched(const float* src, float* dst, int n, long rp, float scale,
                        hipStream_t s);
 void launch_from_pitched(const float* src, float* dst, int n, long rp, hipStream_t s);
+// dense half spectrum [n][n][n/2+1] -> workspace layout (to_ws) or back
+void launch_spec_copy(const float2* src, float2* dst, int n, int cs, bool to_ws, hipStream_t s);
 // AoS [P][3] component j -> pitched mesh j (three meshes).
 void launch_deinterleave(const float* v, float* dst, long dstStride, int np, long rp,
                          hipStream_t s);

@@ -30,6 +30,7 @@
 #include <type_traits>
 
 #include "kernels.h"
+#include "layout.h"
 #include "xcd.h"
 
 namespace pmx {
@@ -374,7 +375,7 @@ k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, 
         float* o = out + comp * outStride;
         for (int c = threadIdx.x; c < T3; c += kBlock) {
             const int l2 = c % T, l1 = (c / T) % T, l0 = c / (T * T);
-            const long g = ((long)(lo[0] + l0) * L.ng + (lo[1] + l1)) * L.rp + lo[2] + l2;
+            const long g = mesh_row(lo[0] + l0, lo[1] + l1, L.ng) * L.rp + lo[2] + l2;
             const double v = (double)(long long)acc[c] * inv_scale;
             o[g] = VEC ? (float)v : (float)(v - 1.0);
         }
@@ -409,6 +410,7 @@ struct GatherArgs {
     const float* mesh;    // 3 meshes mStride apart (1 for kWgrad)
     long mStride;
     long pitch;           // real-row pitch of the meshes
+    int dense;            // 1: meshes in plain row order (a caller's [Ng]^3 array)
     float coeff;          // kick coefficient, or the mesh scale for kWgrad
     float drift;
     int flag;             // kKickDrift: drift?; kWgrad: 1 full reverse step, 2 xi only
@@ -442,8 +444,9 @@ k_gather_tile(GatherArgs A, Lattice L, int nt, const uint32_t* __restrict__ offs
     if (pbeg < pend) {   // uniform across the work-group
         for (int c = threadIdx.x; c < TH3; c += NTH) {
             const int l2 = c % TH, l1 = (c / TH) % TH, l0 = c / (TH * TH);
-            const long g = ((long)((lo[0] + l0) & mask) * L.ng + ((lo[1] + l1) & mask)) * A.pitch +
-                           ((lo[2] + l2) & mask);
+            const int i0 = (lo[0] + l0) & mask, i1 = (lo[1] + l1) & mask;
+            const long row = A.dense ? (long)i0 * L.ng + i1 : mesh_row(i0, i1, L.ng);
+            const long g = row * A.pitch + ((lo[2] + l2) & mask);
 #pragma unroll
             for (int m = 0; m < NM; ++m) mf[m * TH3 + c] = A.mesh[m * A.mStride + g];
         }
@@ -673,7 +676,7 @@ k_ic_state(const float* __restrict__ sm, long sStride, long rp, float D0, float 
          p += (long)gridDim.x * kBlock) {
         int jj[3];
         lattice_index(p, L.np, jj);
-        const long o = ((long)jj[0] * L.np + jj[1]) * rp + jj[2];
+        const long o = mesh_row(jj[0], jj[1], L.np) * rp + jj[2];
         float s[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) s[a] = sm[a * sStride + o];
@@ -701,7 +704,7 @@ k_ic_check(const float* __restrict__ sm, long sStride, long rp, float D0, float 
         // the state is in sorted order: compare with the ICs of lattice particle id[p]
         int jj[3];
         lattice_index(id[p], L.np, jj);
-        const long o = ((long)jj[0] * L.np + jj[1]) * rp + jj[2];
+        const long o = mesh_row(jj[0], jj[1], L.np) * rp + jj[2];
         float s[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) s[a] = sm[a * sStride + o];
@@ -734,7 +737,7 @@ k_to_pitched(const float* __restrict__ src, float* __restrict__ dst, int n, long
     const long N = (long)n * n * n;
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < N; i += (long)gridDim.x * kBlock) {
         const long row = i / n;
-        dst[row * rp + (i % n)] = scale * src[i];
+        dst[mesh_row((int)(row / n), (int)(row % n), n) * rp + (i % n)] = scale * src[i];
     }
 }
 
@@ -743,7 +746,21 @@ k_from_pitched(const float* __restrict__ src, float* __restrict__ dst, int n, lo
     const long N = (long)n * n * n;
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < N; i += (long)gridDim.x * kBlock) {
         const long row = i / n;
-        dst[i] = src[row * rp + (i % n)];
+        dst[i] = src[mesh_row((int)(row / n), (int)(row % n), n) * rp + (i % n)];
+    }
+}
+
+// Half spectrum [n][n][n/2+1] (dense, plain row order) <-> the workspace layout
+// (rows of cs values in the blocked order of layout.h).
+__global__ void __launch_bounds__(kBlock)
+k_spec_copy(const float2* __restrict__ src, float2* __restrict__ dst, int n, int cs, int to_ws) {
+    const int h = n / 2 + 1;
+    const long N = (long)n * n * h;
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < N; i += (long)gridDim.x * kBlock) {
+        const long row = i / h;
+        const long w = mesh_row((int)(row / n), (int)(row % n), n) * cs + (i % h);
+        if (to_ws) dst[w] = src[i];
+        else dst[i] = src[w];
     }
 }
 
@@ -752,7 +769,8 @@ k_deinterleave(const float* __restrict__ v, float* __restrict__ dst, long dstStr
     const long P = (long)np * np * np;
     for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
          p += (long)gridDim.x * kBlock) {
-        const long o = (p / np) * rp + (p % np);
+        const long row = p / np;
+        const long o = mesh_row((int)(row / np), (int)(row % np), np) * rp + (p % np);
 #pragma unroll
         for (int a = 0; a < 3; ++a) dst[a * dstStride + o] = v[3 * p + a];
     }
@@ -804,7 +822,7 @@ k_pk_bin(const float2* __restrict__ spec, int n, int cs, int nbins, double* __re
         const double kn = sqrt((double)nsq);
         const int b = (int)floor(kn + 0.5);
         if (b < 1 || b > nbins) continue;
-        const float2 d = spec[row * cs + k2];
+        const float2 d = spec[mesh_row(i0, i1, n) * cs + k2];
         const double w = (k2 == 0 || k2 == n / 2) ? 1.0 : 2.0;
         atomicAdd(&sb[3 * (b - 1)], w * ((double)d.x * d.x + (double)d.y * d.y));
         atomicAdd(&sb[3 * (b - 1) + 1], w * kn);
@@ -826,10 +844,11 @@ k_radial_scale(float2* __restrict__ spec, int n, int cs, const float* __restrict
         const int i1 = (int)(row % n), i0 = (int)(row / n);
         const int n0 = i0 < n / 2 ? i0 : i0 - n, n1 = i1 < n / 2 ? i1 : i1 - n;
         const float t = table[n0 * n0 + n1 * n1 + k2 * k2];
-        float2 d = spec[row * cs + k2];
+        const long o = mesh_row(i0, i1, n) * cs + k2;
+        float2 d = spec[o];
         d.x *= t;
         d.y *= t;
-        spec[row * cs + k2] = d;
+        spec[o] = d;
     }
 }
 
@@ -999,12 +1018,13 @@ void launch_unkick_vjp(const uint32_t* xq, int32_t* pq, const float* fmesh, long
 
 void launch_wgrad(const float* mesh, long pitch, float g_scale, uint32_t* xq, const int32_t* pq,
                   float* xi, float* pi, const Lattice& L, const Bins& b, float drift, int mode,
-                  double* partials, hipStream_t s) {
+                  double* partials, hipStream_t s, bool dense) {
     GatherArgs A{};
     A.xq = xq;
     A.pq = const_cast<int32_t*>(pq);
     A.mesh = mesh;
     A.pitch = pitch;
+    A.dense = dense ? 1 : 0;
     A.coeff = g_scale;
     A.drift = drift;
     A.flag = mode;
@@ -1083,6 +1103,12 @@ void launch_to_pitched(const float* src, float* dst, int n, long rp, float scale
 void launch_from_pitched(const float* src, float* dst, int n, long rp, hipStream_t s) {
     const long N = (long)n * n * n;
     hipLaunchKernelGGL(k_from_pitched, dim3(grid_for(N)), dim3(kBlock), 0, s, src, dst, n, rp);
+}
+
+void launch_spec_copy(const float2* src, float2* dst, int n, int cs, bool to_ws, hipStream_t s) {
+    const long N = (long)n * n * (n / 2 + 1);
+    hipLaunchKernelGGL(k_spec_copy, dim3(grid_for(N)), dim3(kBlock), 0, s, src, dst, n, cs,
+                       to_ws ? 1 : 0);
 }
 
 void launch_deinterleave(const float* v, float* dst, long dstStride, int np, long rp,

@@ -720,7 +720,7 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
     if (g_dens) {
         KTimer t(ctx, PM_K_WGRAD, 24.0 * P + mesh_r(ctx->ng));
         launch_wgrad(g_dens, ctx->ng, mass, ctx->xq, ctx->pq, ctx->xi, ctx->pi, ctx->lat,
-                     ctx->bins, 0.f, 2, nullptr, s);
+                     ctx->bins, 0.f, 2, nullptr, s, true);
     }
     {
         KTimer t(ctx, PM_K_UNKICK_VJP, bytes_unkick);
@@ -1009,12 +1009,10 @@ int pm_fft_r2c(pm_ctx* ctx, const float* real, float* spec) {
     PM_TRY(ctx_check(ctx));
     if (!real || !spec) return ctx->fail(PM_EINVAL, "real and spec are required");
     hipStream_t s = ctx->stream;
-    const int ng = ctx->ng, h = ng / 2 + 1;
+    const int ng = ctx->ng;
     launch_to_pitched(real, ctx->creal(0), ng, ctx->lat.rp, 1.f, s);
     launch_fft3_r2c(ctx->C[0], ng, ctx->cs, 1, ctx->plan.cplx_elems, ctx->twd, s);
-    if (hipMemcpy2DAsync(spec, h * sizeof(float2), ctx->C[0], ctx->cs * sizeof(float2),
-                         h * sizeof(float2), (size_t)ng * ng, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return ctx->fail(PM_EHIP, "copy of the spectrum failed");
+    launch_spec_copy(ctx->C[0], reinterpret_cast<float2*>(spec), ng, ctx->cs, false, s);
     return ctx->hip_check("pm_fft_r2c");
 }
 
@@ -1022,10 +1020,8 @@ int pm_fft_c2r(pm_ctx* ctx, const float* spec, float* real) {
     PM_TRY(ctx_check(ctx));
     if (!real || !spec) return ctx->fail(PM_EINVAL, "real and spec are required");
     hipStream_t s = ctx->stream;
-    const int ng = ctx->ng, h = ng / 2 + 1;
-    if (hipMemcpy2DAsync(ctx->C[0], ctx->cs * sizeof(float2), spec, h * sizeof(float2),
-                         h * sizeof(float2), (size_t)ng * ng, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return ctx->fail(PM_EHIP, "copy of the spectrum failed");
+    const int ng = ctx->ng;
+    launch_spec_copy(reinterpret_cast<const float2*>(spec), ctx->C[0], ng, ctx->cs, true, s);
     launch_fft3_c2r(ctx->C[0], ng, ctx->cs, 1, ctx->plan.cplx_elems, ctx->twd, s);
     launch_from_pitched(ctx->creal(0), real, ng, ctx->lat.rp, s);
     return ctx->hip_check("pm_fft_c2r");

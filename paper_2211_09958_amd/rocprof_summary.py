@@ -35,8 +35,8 @@ MARKER = "FillFunctor<unsigned char>"
 CALIB = "__amd_rocclr_copyBuffer"
 
 
-FFT_SOURCES = ("fft.hip", "fft_engine.h", "fft_plan.h", "xcd.h")
-PARTICLE_SOURCES = ("particles.hip", "xcd.h")
+FFT_SOURCES = ("fft.hip", "fft_engine.h", "fft_plan.h", "layout.h", "xcd.h")
+PARTICLE_SOURCES = ("particles.hip", "layout.h", "xcd.h")
 FAMILY_SOURCES = {"fft_x": FFT_SOURCES, "fft_strided": FFT_SOURCES, "grad_z": FFT_SOURCES,
                   "grad_adj_z": FFT_SOURCES, "scatter": PARTICLE_SOURCES,
                   "scatter_vec": PARTICLE_SOURCES, "gather": PARTICLE_SOURCES,
