@@ -1,0 +1,93 @@
+"""Field-level reconstruction of initial conditions through the reverse-time adjoint.
+
+The paper's use of gradients: fit the initial white-noise modes of a PM simulation
+to an observed final density by gradient descent through the adjoint.  Here the
+"observed" field is the final CIC density of a run from a held-back seed; the fit
+starts from zero noise and minimises L(w) = Ng^-3 Sum (delta(w) - delta_obs)^2 with
+Adam on the Np^3 noise values.  Every step runs in libpmx: forward run, MSE loss
+and its cotangent, reverse-time adjoint to dL/dw, Adam, and the power spectra
+behind the reported cross-correlation r(k) = P_rt / sqrt(P_rr P_tt) of the
+reconstructed and true noise (P_rt = [P(r + t) - P(r - t)] / 4).
+
+    python -m paper_2211_09958_amd.reconstruct --ptcl 64 --mesh 128 --box 128 --steps 15 \
+        --iters 100 --report recon.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+from synthetic import Cosmology, white_noise  # noqa: E402  (seeded inputs only)
+
+
+def parse(argv=None):
+    p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    p.add_argument("--ptcl", type=int, default=64)
+    p.add_argument("--mesh", type=int, default=128)
+    p.add_argument("--box", type=float, default=128.0)
+    p.add_argument("--steps", type=int, default=15)
+    p.add_argument("--true-seed", type=int, default=7)
+    p.add_argument("--iters", type=int, default=100)
+    p.add_argument("--lr", type=float, default=0.05)
+    p.add_argument("--log-every", type=int, default=10)
+    p.add_argument("--report", default="")
+    return p.parse_args(argv)
+
+
+def cross_correlation(ctx, a, b, n_bins):
+    """r(k) of two [n]^3 fields in shells 1..n_bins, from pm_power_spectrum on a
+    context whose mesh is n (polarisation: P_ab = [P(a + b) - P(a - b)] / 4)."""
+    pa = ctx.power_spectrum(a, n_bins)[1]
+    pb = ctx.power_spectrum(b, n_bins)[1]
+    pab = (ctx.power_spectrum((a + b).contiguous(), n_bins)[1]
+           - ctx.power_spectrum((a - b).contiguous(), n_bins)[1]) / 4.0
+    return pab / np.sqrt(pa * pb)
+
+
+def main(argv=None):
+    a = parse(argv)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    pm = api.PMContext(api.make_config(a.ptcl, a.mesh, a.box, a.steps), Cosmology(), device=dev)
+    w_true = torch.as_tensor(white_noise(a.ptcl, a.true_seed), dtype=torch.float32, device=dev)
+    _, _, obs = pm.forward(w_true)
+    obs = obs.clone()
+    w = torch.zeros_like(w_true)
+    m = torch.zeros(w.numel(), dtype=torch.float32, device=dev)
+    v = torch.zeros_like(m)
+    history = []
+    t0 = time.perf_counter()
+    for it in range(1, a.iters + 1):
+        _, _, dens = pm.forward(w)
+        loss, g = pm.loss_mse(dens, obs)
+        g_w, _, _ = pm.adjoint(g_dens=g)
+        pm.adam(w.view(-1), g_w.view(-1), m, v, it, lr=a.lr)
+        history.append({"iter": it, "loss": loss})
+        if it % a.log_every == 0 or it == 1:
+            print(f"iter {it:4d}  loss {loss:.4e}  {time.perf_counter() - t0:.1f} s", flush=True)
+    grid = api.PMContext(api.make_config(a.ptcl, a.ptcl, a.box, 1), Cosmology(), device=dev)
+    r = cross_correlation(grid, w, w_true, a.ptcl // 2)
+    report = {"config": vars(a), "seconds": time.perf_counter() - t0, "history": history,
+              "loss_first": history[0]["loss"], "loss_last": history[-1]["loss"],
+              "noise_cross_correlation": r.tolist()}
+    print(f"loss {history[0]['loss']:.4e} -> {history[-1]['loss']:.4e}; noise cross-correlation "
+          f"with the truth r(k) at shells 1,2,4,8: "
+          + ", ".join(f"{r[i - 1]:.3f}" for i in (1, 2, 4, 8) if i <= len(r)), flush=True)
+    if a.report:
+        with open(a.report, "w") as f:
+            json.dump(report, f, indent=1)
+    return report
+
+
+if __name__ == "__main__":
+    main()
