@@ -172,10 +172,24 @@ def main():
                 "avg_launch_ms": f["ms"] / max(f["launches"], 1),
                 "algorithmic_bytes_per_launch": per_launch}
     total_ms = sum(v["ms"] for v in fams.values())
-    breakdown = {k: {"ms_per_step": v["ms"] / args.steps,
-                     "share": v["ms"] / total_ms if total_ms else 0.0,
-                     "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else 0.0}
-                 for k, v in fams.items() if v["ms"] > 0}
+    breakdown = {}
+    for k, v in fams.items():
+        if v["ms"] <= 0:
+            continue
+        gbps = v["bytes"] / (v["ms"] * 1e-3) / 1e9
+        e = {"ms_per_step": v["ms"] / args.steps, "share": v["ms"] / total_ms,
+             "GBps": gbps, "frac_alg": gbps / PEAK_HBM_GBS}
+        # counter bytes (rocprofv3 FETCH_SIZE + WRITE_SIZE) where the committed
+        # summary was taken on the current kernel sources
+        launches = max(v["launches"], 1)
+        t = traffic_for(k, v["bytes"] / launches) if v["bytes"] > 0 else None
+        if t is not None:
+            e["frac_counter"] = t * launches / (v["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS
+        breakdown[k] = e
+    # the initial conditions and their adjoint (and the reconstruction checks)
+    # are the "other" family: throughput of the time steps alone
+    other_s = fams.get("other", {}).get("ms", 0.0) * 1e-3
+    value_steps_only = P * w.n_steps * args.steps / (dt - other_s) if dt > other_s else None
 
     out = {"metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
@@ -189,6 +203,7 @@ def main():
            "roofline": roofline,
            "reconstruction": {"ic_rms_cells": st["ic_rms_cells"], "ic_max_cells": st["ic_max_cells"],
                               "ckpt_rms_cells": st["ckpt_rms_cells"]},
+           "value_excluding_ics": value_steps_only,
            "grad_cosmo": list(g_cosmo), "kernel_breakdown": breakdown}
 
     if not args.no_pure_variant and args.checkpoint_every:
