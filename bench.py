@@ -25,9 +25,10 @@ sys.path.insert(0, ROOT)
 METRIC = "fwd+adjoint particle-steps/s at 512³/1024³; learned vs plain speed at 2% P(k)"
 PEAK_HBM_GBS = 8000.0
 CPU_STEPS = 10          # oracle sample: about 10-20 s on a 16-core host
-WEIGHTS = os.path.join(ROOT, "paper_2211_09958_amd", "weights", "filter_128p_128m_to_512m.npy")
+# trained against the 2x-finer mesh, the resolution of the plain run it is compared with
+WEIGHTS = os.path.join(ROOT, "paper_2211_09958_amd", "weights", "filter_128p_128m_to_256m.npy")
 FAMILY_KERNELS = {
-    "fft_strided": ["k_fft_strided"], "fft_x": ["k_fft_x_r2c", "k_fft_x_c2r"],
+    "fft_strided": ["k_fft_strided", "k_fft_y_split"], "fft_x": ["k_fft_x_r2c", "k_fft_x_c2r"],
     "grad_z": ["k_grad_z"], "grad_adj_z": ["k_grad_adj_z"],
     "scatter": ["k_scatter_tile<16, false>"], "scatter_vec": ["k_scatter_tile<16, true>"],
     "gather": ["k_gather_tile<16, 0>"], "unkick_vjp": ["k_gather_tile<16, 2>"],

@@ -79,9 +79,12 @@ k_fft_x_r2c(float2* __restrict__ buf, int cs, long nrows, long bufStride,
     }
 }
 
+// kmul_buf >= 0: the spectrum of buffer kmul_buf is first multiplied by i k2
+// (zero on the Nyquist column), i.e. this pass also takes the spectral
+// derivative along the last axis.
 template <int N>
 __global__ void __launch_bounds__(Cfg<N / 2>::T * Cfg<N / 2>::ROWS)
-k_fft_x_c2r(float2* __restrict__ buf, int cs, long nrows, long bufStride,
+k_fft_x_c2r(float2* __restrict__ buf, int cs, long nrows, long bufStride, int kmul_buf,
             const float2* __restrict__ tw, int ntw,
             const float2* __restrict__ st) {
     constexpr int H = N / 2, E = Cfg<H>::E, T = Cfg<H>::T, ROWS = Cfg<H>::ROWS;
@@ -93,10 +96,15 @@ k_fft_x_c2r(float2* __restrict__ buf, int cs, long nrows, long bufStride,
     float2* rowp = buf + blockIdx.y * bufStride + (valid ? row : 0) * cs;
     const int twN = ntw / N;
     float2* L = lds + r * LS;
+    const bool kmul = (int)blockIdx.y == kmul_buf;
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-        L[lpad(j + e * T)] = valid ? rowp[j + e * T] : make_float2(0.f, 0.f);
-    if (j == 0) L[lpad(H)] = valid ? rowp[H] : make_float2(0.f, 0.f);
+    for (int e = 0; e < E; ++e) {
+        const int k = j + e * T;
+        float2 x = valid ? rowp[k] : make_float2(0.f, 0.f);
+        if (kmul) x = make_float2(-(float)k * x.y, (float)k * x.x);
+        L[lpad(k)] = x;
+    }
+    if (j == 0) L[lpad(H)] = (valid && !kmul) ? rowp[H] : make_float2(0.f, 0.f);
     __syncthreads();
     float2 v[E];
 #pragma unroll
@@ -144,10 +152,52 @@ k_fft_strided(float2* __restrict__ buf, int cs, int ncb, long bufStride,
 
 __device__ __forceinline__ int signed_freq(int p, int n) { return p < n / 2 ? p : p - n; }
 
-// Axis-0 pass with the fused gradient multiply (see launch_grad_z).  Along an
-// axis-0 column n1 and n2 are fixed, so F~_1 and F~_2 are i n1 and i n2 times
-// the same inverse transform of radial * delta; only F~_0 needs an inverse
-// transform of its own: three column FFTs per tile instead of four.
+// Inverse axis-1 pass that splits G into the two spectra it feeds: out_g =
+// IFFT_1(G) (F~_2 = i k2 times it, applied by the last-axis C2R) and, in place,
+// F~_1 = IFFT_1(i n1 G) (zero on the Nyquist plane of axis 1).  The column is
+// loaded twice (the second load mostly from L2) so that only one transform's
+// values are held in registers at a time.
+template <int H>
+__global__ void __launch_bounds__(Cfg<H>::T * Cfg<H>::W, Cfg<H>::MINW)
+k_fft_y_split(float2* __restrict__ g, float2* __restrict__ out_g, int cs, int ncb,
+              const float2* __restrict__ tw, int ntw, const float2* __restrict__ st) {
+    constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::W;
+    __shared__ float2 lds[lds_slots(H) * W];
+    const int c = threadIdx.x % W, j = threadIdx.x / W;
+    const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int a = tile / ncb, cb = tile % ncb;   // a: axis-0 index
+    const int k2 = cb * W + c;
+    auto off = [&](int p) -> long { return mesh_row(a, p, H) * cs + k2; };
+    float2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = g[off(j + e * T)];
+    fft_lds<H, E, 1>(v, lds, W, c, j, st);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) out_g[off(j + e * T)] = lds[lpad(j + e * T) * W + c];
+    // compiler-only barrier: the reload must not be hoisted above the first
+    // transform, where its registers would be live alongside it
+    __asm__ volatile("" ::: "memory");
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = j + e * T;
+        const float f1 = p == H / 2 ? 0.f : (float)signed_freq(p, H);
+        const float2 x = g[off(p)];
+        v[e] = make_float2(-f1 * x.y, f1 * x.x);
+    }
+    __syncthreads();   // every lane has read the first transform's output
+    fft_lds<H, E, 1>(v, lds, W, c, j, st);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) g[off(j + e * T)] = lds[lpad(j + e * T) * W + c];
+}
+
+// Axis-0 pass with the fused gradient multiply (see launch_grad_z).  Writes
+// F~_0 = IFFT_0(i n0 radial delta) and G = IFFT_0(radial delta); F~_1 and F~_2
+// are i n1 G and i n2 G, and since n1 and n2 are constant along axis 0 those
+// factors are applied by the later passes (k_fft_y_split multiplies by i n1
+// before its axis-1 transform, the last-axis C2R by i k2), so this pass stores
+// two spectra instead of three.
 template <int H>
 __global__ void __launch_bounds__(Cfg<H>::T * Cfg<H>::W)
 k_grad_z(const float2* __restrict__ src, float2* __restrict__ dst, long dstStride, int cs,
@@ -183,18 +233,9 @@ k_grad_z(const float2* __restrict__ src, float2* __restrict__ dst, long dstStrid
     fft_lds<H, E, 1>(v, lds, W, c, j, st);
     __syncthreads();
     {
-        // i n_j g for j = 1, 2 (zero on the Nyquist plane of the axis)
-        const float f1 = n1 == -n / 2 ? 0.f : (float)n1;
-        const float f2 = k2 == n / 2 ? 0.f : (float)k2;
-        float2* o1 = dst + dstStride;
-        float2* o2 = dst + 2 * dstStride;
+        float2* og = dst + dstStride;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const float2 g = lds[lpad(j + e * T) * W + c];
-            const long o = off(j + e * T);
-            o1[o] = make_float2(-g.y * f1, g.x * f1);
-            o2[o] = make_float2(-g.y * f2, g.x * f2);
-        }
+        for (int e = 0; e < E; ++e) og[off(j + e * T)] = lds[lpad(j + e * T) * W + c];
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -326,12 +367,13 @@ void x_r2c(float2* buf, int cs, int nbuf, long bufStride, const Twiddles& tw,
 }
 
 template <int N>
-void x_c2r(float2* buf, int cs, int nbuf, long bufStride, const Twiddles& tw,
+void x_c2r(float2* buf, int cs, int nbuf, long bufStride, int kmul_buf, const Twiddles& tw,
            hipStream_t s) {
     constexpr int ROWS = Cfg<N / 2>::ROWS, T = Cfg<N / 2>::T;
     long nrows = (long)N * N;
     dim3 grid((unsigned)((nrows + ROWS - 1) / ROWS), nbuf);
-    hipLaunchKernelGGL(k_fft_x_c2r<N>, grid, dim3(T * ROWS), 0, s, buf, cs, nrows, bufStride, tw.w, tw.n, tw.stages);
+    hipLaunchKernelGGL(k_fft_x_c2r<N>, grid, dim3(T * ROWS), 0, s, buf, cs, nrows, bufStride,
+                       kmul_buf, tw.w, tw.n, tw.stages);
 }
 
 template <int N>
@@ -356,7 +398,25 @@ void launch_fft_x_r2c(float2* buf, int n, int cs, int nbuf, long bufStride, cons
 }
 
 void launch_fft_x_c2r(float2* buf, int n, int cs, int nbuf, long bufStride, const Twiddles& tw, hipStream_t s) {
-    size_switch(n, [&](auto nn) { x_c2r<decltype(nn)::value>(buf, cs, nbuf, bufStride, tw, s); });
+    size_switch(n, [&](auto nn) { x_c2r<decltype(nn)::value>(buf, cs, nbuf, bufStride, -1, tw, s); });
+}
+
+void launch_fft_x_c2r_dk2(float2* buf, int n, int cs, int nbuf, long bufStride, int kmul_buf,
+                          const Twiddles& tw, hipStream_t s) {
+    size_switch(n, [&](auto nn) {
+        x_c2r<decltype(nn)::value>(buf, cs, nbuf, bufStride, kmul_buf, tw, s);
+    });
+}
+
+void launch_fft_y_split(float2* g, float2* out_g, int n, int cs, const Twiddles& tw,
+                        hipStream_t s) {
+    size_switch(n, [&](auto nn) {
+        constexpr int N = decltype(nn)::value;
+        constexpr int W = Cfg<N>::W, T = Cfg<N>::T;
+        const int ncb = cs / W;
+        hipLaunchKernelGGL(k_fft_y_split<N>, dim3(N * ncb), dim3(T * W), 0, s, g, out_g, cs, ncb,
+                           tw.w, tw.n, tw.stages);
+    });
 }
 
 void launch_fft_axis(float2* buf, int n, int cs, int axis, int dir, int nbuf, long bufStride,

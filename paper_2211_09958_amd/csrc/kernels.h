@@ -30,13 +30,20 @@ void fill_stage_twiddles(float2* table);
 void launch_fft_x_r2c(float2* buf, int n, int cs, int nbuf, long bufStride, const Twiddles& tw, hipStream_t s);
 // Inverse of the above without the 1/n factor (Hermitian rows assumed).
 void launch_fft_x_c2r(float2* buf, int n, int cs, int nbuf, long bufStride, const Twiddles& tw, hipStream_t s);
+// as launch_fft_x_c2r, with buffer kmul_buf multiplied by i k2 first
+void launch_fft_x_c2r_dk2(float2* buf, int n, int cs, int nbuf, long bufStride, int kmul_buf,
+                          const Twiddles& tw, hipStream_t s);
+// inverse axis-1 pass of G: out_g = IFFT_1(G), g <- IFFT_1(i n1 G)
+void launch_fft_y_split(float2* g, float2* out_g, int n, int cs, const Twiddles& tw,
+                        hipStream_t s);
 // Complex transform along axis 0 or 1, in place; dir = -1 forward, +1 inverse.
 void launch_fft_axis(float2* buf, int n, int cs, int axis, int dir, int nbuf, long bufStride,
                      const Twiddles& tw, hipStream_t s);
 // Fused axis-0 pass of the force: forward axis-0 FFT of src (already
-// transformed along axes 2 and 1), multiply by M_j = i n_j radial[|n|^2] for
-// j = 0, 1, 2 (zero on the Nyquist plane of axis j), inverse axis-0 FFT, store
-// to dst + j*dstStride.
+// transformed along axes 2 and 1), then dst = IFFT_0(i n0 radial delta) (zero
+// on the Nyquist plane of axis 0) and dst + dstStride = G = IFFT_0(radial
+// delta); launch_fft_y_split and launch_fft_x_c2r_dk2 turn G into the axis-1
+// and axis-2 components.
 void launch_grad_z(const float2* src, float2* dst, long dstStride, int n, int cs,
                    const float* radial, const Twiddles& tw, hipStream_t s);
 // Fused axis-0 pass of the transpose: dst = inverse-axis-0 of

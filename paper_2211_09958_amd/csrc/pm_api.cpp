@@ -356,11 +356,15 @@ void compute_force(pm_ctx* ctx, double a, bool cotangents) {
       launch_fft_axis(ctx->C[0], ng, cs, 1, -1, 1, cst, ctx->twd, s); }
     const float* radial;
     { KTimer t(ctx, PM_K_MLP, 0); radial = force_radial(ctx, a); }
-    { KTimer t(ctx, PM_K_GRAD_Z, 4 * c);
+    // F~_0 -> C1 and G -> C2; axis 1: F~_0 in place, G -> F~_1 (C2) and IFFT_1(G)
+    // (C3); last axis: C2R of the three, C3 times i k2 first (= F~_2)
+    { KTimer t(ctx, PM_K_GRAD_Z, 3 * c);
       launch_grad_z(ctx->C[0], ctx->C[1], cst, ng, cs, radial, ctx->twd, s); }
-    { KTimer t(ctx, PM_K_FFT_STRIDED, 6 * c);
-      launch_fft_axis(ctx->C[1], ng, cs, 1, 1, 3, cst, ctx->twd, s); }
-    { KTimer t(ctx, PM_K_FFT_X, 3 * (r + c)); launch_fft_x_c2r(ctx->C[1], ng, cs, 3, cst, ctx->twd, s); }
+    { KTimer t(ctx, PM_K_FFT_STRIDED, 5 * c);
+      launch_fft_axis(ctx->C[1], ng, cs, 1, 1, 1, cst, ctx->twd, s);
+      launch_fft_y_split(ctx->C[2], ctx->C[3], ng, cs, ctx->twd, s); }
+    { KTimer t(ctx, PM_K_FFT_X, 3 * (r + c));
+      launch_fft_x_c2r_dk2(ctx->C[1], ng, cs, 3, cst, 2, ctx->twd, s); }
 }
 
 // delta_bar (real, in C0) = transposed spectral operator applied to the CIC
@@ -409,8 +413,9 @@ void ic_synthesis(pm_ctx* ctx, const float* radial, float* s_out, uint32_t* xq, 
     launch_fft_x_r2c(ctx->C[0], np, cs, 1, cst, ctx->twd, s);
     launch_fft_axis(ctx->C[0], np, cs, 1, -1, 1, cst, ctx->twd, s);
     launch_grad_z(ctx->C[0], ctx->C[1], cst, np, cs, radial, ctx->twd, s);
-    launch_fft_axis(ctx->C[1], np, cs, 1, 1, 3, cst, ctx->twd, s);
-    launch_fft_x_c2r(ctx->C[1], np, cs, 3, cst, ctx->twd, s);
+    launch_fft_axis(ctx->C[1], np, cs, 1, 1, 1, cst, ctx->twd, s);
+    launch_fft_y_split(ctx->C[2], ctx->C[3], np, cs, ctx->twd, s);
+    launch_fft_x_c2r_dk2(ctx->C[1], np, cs, 3, cst, 2, ctx->twd, s);
     launch_ic_state(ctx->creal(1), ctx->creal_stride(), rp, (float)ctx->sched.D0,
                     (float)ctx->sched.G0, ctx->lat, xq, pq, id, s_out, s);
 }

@@ -80,8 +80,10 @@ def family(sym: str, ng: int):
         return "fft_x", "rc_per_buf"
     if base == "k_fft_strided" and targs[:1] == [str(ng)]:
         return "fft_strided", "2c_per_buf"
+    if base == "k_fft_y_split" and targs[:1] == [str(ng)]:
+        return "fft_strided", "3c"
     if base == "k_grad_z" and targs[:1] == [str(ng)]:
-        return "grad_z", "4c"
+        return "grad_z", "3c"
     if base == "k_grad_adj_z" and targs[:1] == [str(ng)]:
         return "grad_adj_z", "5c" if targs[1:] == ["true"] else "4c"
     if base == "k_scatter_tile":
@@ -100,7 +102,7 @@ def family(sym: str, ng: int):
 def alg_bytes(rule, grid_y, P, ng):
     r = 4.0 * ng ** 3
     c = 8.0 * ng * ng * (ng // 2 + 1)
-    return {"rc_per_buf": grid_y * (r + c), "2c_per_buf": grid_y * 2 * c, "4c": 4 * c,
+    return {"rc_per_buf": grid_y * (r + c), "2c_per_buf": grid_y * 2 * c, "3c": 3 * c, "4c": 4 * c,
             "5c": 5 * c, "24P+3r": 24 * P + 3 * r, "12P+r": 12 * P + r,
             "48P+3r": 48 * P + 3 * r,
             "72P+3r": 72 * P + 3 * r, "84P+r": 84 * P + r}.get(rule)
