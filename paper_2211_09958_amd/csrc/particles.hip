@@ -293,8 +293,12 @@ constexpr int kRanges = 20;
 // max |coeff * v| and the particle count so that no sum can overflow.  Integer
 // LDS atomics are both order-independent (bitwise reproducible results) and far
 // faster on gfx950 than floating-point LDS atomics.
+// Threads per scatter work-group; the 32 KB accumulator tile leaves room for
+// four work-groups per CU, so larger ones keep more waves in flight.
+constexpr int scatter_threads() { return 2 * kBlock; }
+
 template <int T, bool VEC>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(scatter_threads())
 k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, float coeff,
                const unsigned* __restrict__ vmax_bits, Lattice L, int nt,
                const uint32_t* __restrict__ offsets, float* __restrict__ out, long outStride) {
@@ -335,10 +339,10 @@ k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, 
     const uint32_t total = pre[kRanges];
     constexpr int NC = VEC ? 3 : 1;
     for (int comp = 0; comp < NC; ++comp) {
-        for (int c = threadIdx.x; c < T3; c += kBlock) acc[c] = 0ull;
+        for (int c = threadIdx.x; c < T3; c += scatter_threads()) acc[c] = 0ull;
         __syncthreads();
         // one flat index space over the 20 ranges, so every lane has work
-        for (uint32_t k = threadIdx.x; k < total; k += kBlock) {
+        for (uint32_t k = threadIdx.x; k < total; k += scatter_threads()) {
             int r = 0;
             while (pre[r + 1] <= k) ++r;
             const long p = rs[r] + (k - pre[r]);   // particles are stored in bin order
@@ -373,7 +377,7 @@ k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, 
         }
         __syncthreads();
         float* o = out + comp * outStride;
-        for (int c = threadIdx.x; c < T3; c += kBlock) {
+        for (int c = threadIdx.x; c < T3; c += scatter_threads()) {
             const int l2 = c % T, l1 = (c / T) % T, l0 = c / (T * T);
             const long g = mesh_row(lo[0] + l0, lo[1] + l1, L.ng) * L.rp + lo[2] + l2;
             const double v = (double)(long long)acc[c] * inv_scale;
@@ -919,15 +923,15 @@ static void scatter_dispatch(const uint32_t* xq, const float* v, float coeff, co
     const unsigned ntiles = (unsigned)b.nt * b.nt * b.nt;
     switch (b.tile) {
         case 4:
-            hipLaunchKernelGGL((k_scatter_tile<4, VEC>), dim3(ntiles), dim3(kBlock), 0, s, xq, v,
+            hipLaunchKernelGGL((k_scatter_tile<4, VEC>), dim3(ntiles), dim3(scatter_threads()), 0, s, xq, v,
                                coeff, vmax, L, b.nt, b.offsets, out, outStride);
             break;
         case 8:
-            hipLaunchKernelGGL((k_scatter_tile<8, VEC>), dim3(ntiles), dim3(kBlock), 0, s, xq, v,
+            hipLaunchKernelGGL((k_scatter_tile<8, VEC>), dim3(ntiles), dim3(scatter_threads()), 0, s, xq, v,
                                coeff, vmax, L, b.nt, b.offsets, out, outStride);
             break;
         default:
-            hipLaunchKernelGGL((k_scatter_tile<16, VEC>), dim3(ntiles), dim3(kBlock), 0, s, xq, v,
+            hipLaunchKernelGGL((k_scatter_tile<16, VEC>), dim3(ntiles), dim3(scatter_threads()), 0, s, xq, v,
                                coeff, vmax, L, b.nt, b.offsets, out, outStride);
             break;
     }
