@@ -430,7 +430,7 @@ struct GatherArgs {
 // Threads per gather work-group: the three-mesh tile takes 59 KB of LDS (two
 // work-groups per CU), so those modes use larger work-groups to keep more waves
 // in flight.
-constexpr int gather_threads(int mode) { return mode == kWgrad ? kBlock : 2 * kBlock; }
+constexpr int gather_threads(int mode) { return mode == kWgrad ? kBlock : 4 * kBlock; }
 
 template <int T, int MODE>
 __global__ void __launch_bounds__(gather_threads(MODE))
