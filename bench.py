@@ -272,10 +272,14 @@ def learned_vs_plain(args, co, noise, disp_plain, plain_value):
     plain = api.PMContext(api.config_from_workload(w), co, device="cuda:0")
     pk_plain = plain.power_spectrum(plain.forward(noise)[2], w.mesh // 2)[1]
     err = lambda pk: float(np.max(np.abs(pk[:half] / pk_ref[:half] - 1.0)))
+    worst = lambda pk: int(np.argmax(np.abs(pk[:half] / pk_ref[:half] - 1.0))) + 1
     e_l, e_p = err(pk_learned), err(pk_plain)
     return {"workload": f"{w.name} learned f(|k|,a)", "value": value, "unit": "particle-steps/s",
             "ms_per_step": dt / args.steps * 1e3, "speedup_vs_plain_1024": value / plain_value,
             "pk_maxerr_to_half_nyq": {"learned_512": e_l, "plain_512": e_p},
+            "worst_shell": {"learned_512": worst(pk_learned), "plain_512": worst(pk_plain)},
+            "pk_ratio_learned_shells_1_16": [round(float(x), 4) for x in
+                                             (pk_learned[:16] / pk_ref[:16])],
             "reference": "plain 512^3 particles on the 1024^3 mesh, same seed; all P(k) on the "
                          "512^3 mesh",
             "within_2pct": e_l <= 0.02, "weights": os.path.relpath(args.weights, ROOT)}
