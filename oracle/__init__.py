@@ -21,6 +21,8 @@ Modules
   mesh       cloud-in-cell scatter/gather/gradient, spectral Poisson force,
              power spectrum and its transpose
   mlp        the 2-64-64-1 SiLU force filter, forward and backward
+  lpt        second-order (2LPT) initial-condition term, its transpose and
+             Omega_m tangent
   pm         initial conditions, KDK time stepping, discrete adjoint over a
              stored trajectory, gradients w.r.t. noise, Omega_m, sigma_8 and
              filter weights; the filter-training losses

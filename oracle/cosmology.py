@@ -14,6 +14,9 @@ Passages followed
   * Eisenstein & Hu 1998 no-wiggle transfer function.
   * FastPM growth-factor coefficients: each kick/drift factor is chosen so
     that one step is exact for linear (Zel'dovich) growth.
+  * Second-order growth for 2LPT initial conditions: the fit
+    D2 = -(3/7) D^2 Omega_m(a)^(-1/143) (Bouchet et al. 1995), with
+    Omega_m(a) = Omega_m a^-3 / E^2; exactly -(3/7) D^2 in the matter era.
 """
 from __future__ import annotations
 
@@ -62,6 +65,32 @@ def growth_G(a, omega_m):
     """Momentum growth G(a) = a^3 E(a) dD/da, so that p = G s in linear theory."""
     a = np.asarray(a, dtype=np.float64)
     return a ** 3 * hubble_E(a, omega_m) * growth_dD(a, omega_m)
+
+
+def omega_m_of_a(a, omega_m):
+    """Matter density parameter at a: Omega_m a^-3 / E(a)^2."""
+    a = np.asarray(a, dtype=np.float64)
+    return omega_m * a ** -3 / hubble_E(a, omega_m) ** 2
+
+
+def growth_D2(a, omega_m):
+    """Second-order growth D2(a) = -(3/7) D(a)^2 Omega_m(a)^(-1/143)."""
+    return (-3.0 / 7.0) * growth_D(a, omega_m) ** 2 * omega_m_of_a(a, omega_m) ** (-1.0 / 143.0)
+
+
+def growth_dD2(a, omega_m):
+    """dD2/da of the fit: D2 [2 D'/D + (3/143) (1 - Omega_m(a)) / a], using
+    dln Omega_m(a)/da = -3 (1 - Omega_m(a)) / a."""
+    a = np.asarray(a, dtype=np.float64)
+    dlog = (2.0 * growth_dD(a, omega_m) / growth_D(a, omega_m)
+            + (3.0 / 143.0) * (1.0 - omega_m_of_a(a, omega_m)) / a)
+    return growth_D2(a, omega_m) * dlog
+
+
+def growth_G2(a, omega_m):
+    """Second-order momentum growth G2 = a^3 E dD2/da (p = G2 s2 at second order)."""
+    a = np.asarray(a, dtype=np.float64)
+    return a ** 3 * hubble_E(a, omega_m) * growth_dD2(a, omega_m)
 
 
 def growth_D_integral(a, omega_m):
@@ -160,6 +189,8 @@ class KDKCoefficients:
     kick_b: np.ndarray   # second half-kick of step n
     D0: float            # D(a_0), scales the Zel'dovich displacement
     G0: float            # G(a_0), scales the Zel'dovich momentum
+    D20: float = 0.0     # D2(a_0), scales the second-order displacement
+    G20: float = 0.0     # G2(a_0), scales the second-order momentum
 
 
 def kdk_coefficients(omega_m, a_start, a_stop, n_steps):
@@ -181,11 +212,13 @@ def kdk_coefficients(omega_m, a_start, a_stop, n_steps):
     drift = (D[1:] - D[:-1]) / Gh
     kick_b = (G[1:] - Gh) / D[1:]
     return KDKCoefficients(a=a, kick_a=kick_a, drift=drift, kick_b=kick_b,
-                           D0=float(D[0]), G0=float(G[0]))
+                           D0=float(D[0]), G0=float(G[0]),
+                           D20=float(growth_D2(a[0], omega_m)),
+                           G20=float(growth_G2(a[0], omega_m)))
 
 
 def kdk_coefficient_derivatives(omega_m, a_start, a_stop, n_steps, rel_step=1e-5):
-    """Central differences in Omega_m of every KDK factor and of D0, G0."""
+    """Central differences in Omega_m of every KDK factor and of D0, G0, D20, G20."""
     h = rel_step * omega_m
     up = kdk_coefficients(omega_m + h, a_start, a_stop, n_steps)
     dn = kdk_coefficients(omega_m - h, a_start, a_stop, n_steps)
@@ -193,4 +226,5 @@ def kdk_coefficient_derivatives(omega_m, a_start, a_stop, n_steps, rel_step=1e-5
     return KDKCoefficients(a=up.a, kick_a=(up.kick_a - dn.kick_a) * inv,
                            drift=(up.drift - dn.drift) * inv,
                            kick_b=(up.kick_b - dn.kick_b) * inv,
-                           D0=(up.D0 - dn.D0) * inv, G0=(up.G0 - dn.G0) * inv)
+                           D0=(up.D0 - dn.D0) * inv, G0=(up.G0 - dn.G0) * inv,
+                           D20=(up.D20 - dn.D20) * inv, G20=(up.G20 - dn.G20) * inv)

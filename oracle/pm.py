@@ -17,7 +17,9 @@ integration.  Agreement of the two therefore checks the reconstruction.
 
 Initial conditions follow the Zel'dovich approximation: the linear density is
 the white noise coloured by sqrt(P(k)/V_cell), the displacement is
-s_k = i k delta_k / k^2, and x_0 = q + D(a_0) s, p_0 = G(a_0) s.
+s_k = i k delta_k / k^2, and x_0 = q + D(a_0) s, p_0 = G(a_0) s.  With
+``lpt_order = 2`` the second-order term of ``lpt`` is added:
+x_0 = q + D s + D2 s2, p_0 = G s + G2 s2.
 
 Time stepping is kick-drift-kick with growth-factor coefficients
 (``cosmology.kdk_coefficients``):
@@ -33,6 +35,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import cosmology as cosmo_mod
+from . import lpt
 from . import mesh as M
 from . import mlp
 
@@ -46,6 +49,7 @@ class Setup:
     cosmo: object
     a_start: float = 1.0 / 64
     a_stop: float = 1.0
+    lpt_order: int = 1            # 1: Zel'dovich ICs; 2: plus the 2LPT term
 
     @property
     def n_particles(self):
@@ -159,6 +163,7 @@ class Run:
     setup: Setup
     theta: object
     s: np.ndarray                 # Zel'dovich displacement at a = 1, [P, 3]
+    s2: np.ndarray = None         # second-order displacement at a = 1 (2LPT)
     disp: list = field(default_factory=list)     # x_n - q, n = 0..N
     p_half: list = field(default_factory=list)   # p_{n+1/2}, n = 0..N-1
     mom0: np.ndarray = None
@@ -171,20 +176,33 @@ class Run:
 
 
 def forward(noise, setup, theta=None):
-    """Zel'dovich ICs then N KDK steps, storing the whole trajectory."""
+    """Zel'dovich (or 2LPT) ICs then N KDK steps, storing the whole trajectory."""
     s = zeldovich_displacement(noise, setup.box,
                                ic_radial(setup.ptcl_grid, setup.box, setup.cosmo))
-    return forward_from_displacement(s, setup, theta)
+    s2 = (lpt.second_order_displacement(noise, setup.box, setup.cosmo)
+          if setup.lpt_order == 2 else None)
+    return forward_from_displacement(s, setup, theta, s2)
 
 
-def forward_from_displacement(s, setup, theta=None):
-    """N KDK steps from x_0 = q + D(a_0) s, p_0 = G(a_0) s for a given s [P, 3]."""
+def initial_state(s, setup, s2=None):
+    """(x_0 - q, p_0) = (D s + D2 s2, G s + G2 s2) at a_0 (s2 term for 2LPT)."""
+    co = cosmo_mod.kdk_coefficients(setup.cosmo.omega_m, setup.a_start, setup.a_stop,
+                                    setup.n_steps)
+    disp, mom = co.D0 * s, co.G0 * s
+    if s2 is not None:
+        disp = disp + co.D20 * s2
+        mom = mom + co.G20 * s2
+    return disp, mom
+
+
+def forward_from_displacement(s, setup, theta=None, s2=None):
+    """N KDK steps from x_0 = q + D(a_0) s (+ D2(a_0) s2), p_0 = G(a_0) s
+    (+ G2(a_0) s2) for given s, s2 [P, 3]."""
     co = cosmo_mod.kdk_coefficients(setup.cosmo.omega_m, setup.a_start, setup.a_stop,
                                     setup.n_steps)
     q = lattice(setup.ptcl_grid, setup.box)
-    disp = co.D0 * s
-    mom = co.G0 * s
-    run = Run(setup=setup, theta=theta, s=s, mom0=mom.copy())
+    disp, mom = initial_state(s, setup, s2)
+    run = Run(setup=setup, theta=theta, s=s, s2=s2, mom0=mom.copy())
     run.disp.append(disp.copy())
     F, _, _ = pm_force(q + disp, setup, filter_at(theta, setup, co.a[0])[0])
     for n in range(setup.n_steps):
@@ -237,6 +255,8 @@ class Gradients:
     G0: float
     xi0: np.ndarray
     pi0: np.ndarray
+    D20: float = 0.0
+    G20: float = 0.0
 
 
 def adjoint(run, noise, g_dens=None, g_disp=None, g_mom=None):
@@ -300,9 +320,22 @@ def adjoint(run, noise, g_dens=None, g_disp=None, g_mom=None):
                                    ic_radial_domega_m(st.ptcl_grid, st.box, st.cosmo))
     g_om = (np.dot(g_ka, dco.kick_a) + np.dot(g_kb, dco.kick_b) + np.dot(g_dr, dco.drift)
             + gD0 * dco.D0 + gG0 * dco.G0 + float(np.sum(s_bar * s_dom)))
+    gD20 = gG20 = 0.0
+    if run.s2 is not None:
+        # 2LPT term: disp_0 += D20 s2, p_0 += G20 s2, s2 quadratic in the noise
+        # (hence the factor 2 in the sigma_8 derivative, s2 ~ sigma_8^2)
+        s2_bar = co.D20 * xi + co.G20 * pi
+        gD20 = float(np.sum(xi * run.s2))
+        gG20 = float(np.sum(pi * run.s2))
+        g_noise = g_noise + lpt.second_order_transpose(np.asarray(noise, dtype=np.float64),
+                                                       s2_bar, st.box, st.cosmo)
+        g_sigma8 += 2.0 * float(np.sum(s2_bar * run.s2)) / st.cosmo.sigma8
+        s2_dom = lpt.second_order_tangent_omega_m(np.asarray(noise, dtype=np.float64),
+                                                  st.box, st.cosmo)
+        g_om += gD20 * dco.D20 + gG20 * dco.G20 + float(np.sum(s2_bar * s2_dom))
     return Gradients(noise=g_noise, omega_m=float(g_om), sigma8=g_sigma8, theta=g_theta,
                      kick_a=g_ka, kick_b=g_kb, drift=g_dr, D0=gD0, G0=gG0,
-                     xi0=xi, pi0=pi)
+                     xi0=xi, pi0=pi, D20=gD20, G20=gG20)
 
 
 # ------------------------------------------------------------- losses
