@@ -72,7 +72,8 @@ typedef struct {
  *   filter           0: plain PM (f = 1); 1: learned radial filter (pm_set_filter)
  *   flags            PM_F_TIMING: time every kernel launch with HIP events on
  *                    the context's stream (per-kernel totals in pm_stats);
- *                    other bits must be 0 */
+ *                    PM_F_2LPT: second-order Lagrangian perturbation theory
+ *                    initial conditions (see pm_forward); other bits must be 0 */
 typedef struct {
     int32_t ptcl_grid;
     int32_t mesh;
@@ -85,6 +86,7 @@ typedef struct {
 } pm_config;
 
 #define PM_F_TIMING 1u
+#define PM_F_2LPT 2u
 
 /* Kernel families reported by PM_F_TIMING (index into pm_stats.kernel_*). */
 enum {
@@ -145,6 +147,13 @@ int pm_host_tables(const pm_config* cfg, const pm_cosmology* cosmo,
                    double* coeffs_host, double* dcoeffs_host,
                    double* growth_host, double* pk_host);
 
+/* Second-order growth of the 2LPT initial conditions at a_0 = a_start (host
+ * only, no GPU): out_host[4] = {D2(a_0), G2(a_0), dD2/dOmega_m, dG2/dOmega_m}
+ * with D2 = -(3/7) D^2 Omega_m(a)^(-1/143), Omega_m(a) = Omega_m a^-3 / E^2
+ * (the Bouchet et al. 1995 fit; -(3/7) D^2 in the matter era), G2 = a^3 E dD2/da
+ * and the Omega_m derivatives by central differences. */
+int pm_lpt2_growth(const pm_config* cfg, const pm_cosmology* cosmo, double* out_host);
+
 /* Create a context.  `workspace_dev` must hold pm_workspace_bytes(cfg) bytes,
  * 256-byte aligned, and stay valid until pm_destroy.  `hip_stream` is a
  * hipStream_t (NULL = the default stream).  Uploads the host tables. */
@@ -166,7 +175,14 @@ int pm_set_filter(pm_ctx* ctx, const float* weights_dev);
 /* Forward simulation.
  *   noise_dev [Np][Np][Np]  unit white noise; the Zel'dovich ICs are
  *            x_0 = q + D(a_0) s, p_0 = G(a_0) s with
- *            s_k = i k sqrt(P(k) / V_cell) noise_k / k^2
+ *            s_k = i k sqrt(P(k) / V_cell) noise_k / k^2 (zero on the Nyquist
+ *            plane of the differentiated axis).  With PM_F_2LPT the standard
+ *            second-order term of Lagrangian perturbation theory is added:
+ *            x_0 += D2(a_0) s2, p_0 += G2(a_0) s2 (pm_lpt2_growth), where
+ *            s2_k = -i k S_k / k^2 and S = Sum_{a<b} (phi_aa phi_bb - phi_ab^2)
+ *            over the Hessian phi_ab = IDFT(k_a k_b delta_k / k^2) of the
+ *            potential of delta_k = sqrt(P/V_cell) noise_k (off-diagonal
+ *            entries zero on the Nyquist planes of a and b)
  *   disp_dev  out [Np^3][3] displacement x_N - q (Mpc/h), not wrapped
  *   mom_dev   out [Np^3][3] momentum p_N
  *   dens_dev  out [Ng]^3 overdensity delta = rho - 1 of x_N (nullable)
@@ -242,6 +258,14 @@ int pm_force_vjp(pm_ctx* ctx, const float* disp_dev, double a, const float* v_de
                  float* xi_dev);
 int pm_fft_r2c(pm_ctx* ctx, const float* real_dev, float* spec_dev);
 int pm_fft_c2r(pm_ctx* ctx, const float* spec_dev, float* real_dev);
+
+/* Initial conditions of pm_forward (Zel'dovich, or 2LPT with PM_F_2LPT) for
+ * noise_dev [Np]^3, without time stepping: disp_dev [Np^3][3] = x_0 - q and
+ * mom_dev [Np^3][3] = p_0, lattice order, exactly the state pm_forward starts
+ * from (same fixed-point rounding).  Uses the workspace; a stored forward run
+ * stays valid for pm_adjoint. */
+int pm_initial_conditions(pm_ctx* ctx, const float* noise_dev, float* disp_dev,
+                          float* mom_dev);
 
 /* Learned-filter training helpers (filter = 1 configs).
  *   pm_filter_table: table_dev [3 (Ng/2)^2 + 1] = f(|n|^2, a) for the current

@@ -18,6 +18,7 @@ STATUS_NAMES = {0: "PM_OK", -1: "PM_EINVAL", -2: "PM_ENOMEM", -3: "PM_EHIP",
 PM_MAX_CHECKPOINTS = 64
 N_FILTER_PARAMS = 4417
 PM_F_TIMING = 1
+PM_F_2LPT = 2
 KERNEL_FAMILIES = ("bin", "scatter", "scatter_vec", "fft_x", "fft_strided", "grad_z",
                    "grad_adj_z", "gather", "unkick_vjp", "wgrad", "mlp", "other")
 
@@ -26,6 +27,7 @@ EXPORTS = ("pm_workspace_bytes", "pm_host_tables", "pm_init", "pm_set_cosmology"
            "pm_set_filter", "pm_forward", "pm_adjoint", "pm_loss_mse", "pm_loss_pk",
            "pm_loss_disp", "pm_power_spectrum",
            "pm_density", "pm_force", "pm_force_vjp", "pm_fft_r2c", "pm_fft_c2r",
+           "pm_lpt2_growth", "pm_initial_conditions",
            "pm_filter_table", "pm_adam", "pm_stats_get", "pm_stats_reset", "pm_destroy",
            "pm_last_error")
 
@@ -88,6 +90,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "pm_force_vjp": (c_int, [P, P, c_double, P, P]),
         "pm_fft_r2c": (c_int, [P, P, P]),
         "pm_fft_c2r": (c_int, [P, P, P]),
+        "pm_lpt2_growth": (c_int, [POINTER(Config), POINTER(Cosmology), P]),
+        "pm_initial_conditions": (c_int, [P, P, P, P]),
         "pm_filter_table": (c_int, [P, c_double, P]),
         "pm_adam": (c_int, [P, P, P, c_int32, P, P, c_int32, c_double, c_double, c_double, c_double,
                             c_int32]),

@@ -27,10 +27,13 @@ def _cosmo_struct(c) -> Cosmology:
 
 
 def make_config(ptcl_grid, mesh, box, n_steps, a_start=1.0 / 64, a_stop=1.0,
-                checkpoint_every=0, filter=False, timing=False) -> Config:
+                checkpoint_every=0, filter=False, timing=False, lpt_order=1) -> Config:
+    """pm_config; lpt_order 2 selects 2LPT initial conditions (PM_F_2LPT)."""
+    if lpt_order not in (1, 2):
+        raise ValueError("lpt_order must be 1 or 2")
+    flags = (_lib.PM_F_TIMING if timing else 0) | (_lib.PM_F_2LPT if lpt_order == 2 else 0)
     return Config(int(ptcl_grid), int(mesh), float(box), float(a_start), float(a_stop),
-                  int(n_steps), int(checkpoint_every), int(bool(filter)),
-                  _lib.PM_F_TIMING if timing else 0)
+                  int(n_steps), int(checkpoint_every), int(bool(filter)), flags)
 
 
 def config_from_workload(w, filter=False, checkpoint_every=None, timing=False) -> Config:
@@ -64,6 +67,15 @@ def host_tables(cfg: Config, cosmo):
             "d_kick_a": dco[:N], "d_drift": dco[N:2 * N], "d_kick_b": dco[2 * N:3 * N],
             "d_D0": dco[3 * N], "d_G0": dco[3 * N + 1],
             "D": gr[:N + 1], "dD": gr[N + 1:2 * N + 2], "G": gr[2 * N + 2:], "pk": pk}
+
+
+def lpt2_growth(cfg: Config, cosmo):
+    """Second-order growth at a_start (no GPU): D2, G2 and their Omega_m derivatives."""
+    import numpy as np
+    out = np.zeros(4)
+    cs = _cosmo_struct(cosmo)
+    check(_lib.load().pm_lpt2_growth(byref(cfg), byref(cs), out.ctypes.data_as(c_void_p)))
+    return {"D2": out[0], "G2": out[1], "d_D2": out[2], "d_G2": out[3]}
 
 
 class PMContext:
@@ -136,6 +148,13 @@ class PMContext:
         dens = self._mesh() if want_density else None
         self._check(self.lib.pm_forward(self.ctx, _ptr(noise), _ptr(disp), _ptr(mom), _ptr(dens)))
         return disp, mom, dens
+
+    def initial_conditions(self, noise):
+        """(x_0 - q, p_0) [P, 3] exactly as pm_forward starts (Zel'dovich or 2LPT)."""
+        noise = self._in(noise, (self.np,) * 3)
+        disp, mom = self._vec(), self._vec()
+        self._check(self.lib.pm_initial_conditions(self.ctx, _ptr(noise), _ptr(disp), _ptr(mom)))
+        return disp, mom
 
     def adjoint(self, g_dens=None, g_disp=None, g_mom=None, want_filter=False, g_filter_out=None):
         """Reverse-time adjoint; g_filter_out (a [4417] tensor) receives the filter

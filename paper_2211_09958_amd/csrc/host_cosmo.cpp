@@ -132,6 +132,13 @@ Schedule schedule_shift(double omega_m, double a_start, double a_stop, int n_ste
     }
     s.D0 = s.D[0];
     s.G0 = s.G[0];
+    // second order: D2 = -(3/7) D^2 Om(a)^(-1/143), G2 = a^3 E dD2/da with
+    // dln D2/da = 2 D'/D + (3/143) (1 - Om(a)) / a
+    const double a0 = s.a[0], E0 = hubble(a0, omega_m);
+    const double om_a = omega_m / (a0 * a0 * a0 * E0 * E0);
+    s.D20 = -3.0 / 7.0 * s.D[0] * s.D[0] * std::pow(om_a, -1.0 / 143.0);
+    s.G20 = a0 * a0 * a0 * E0 * s.D20 *
+            (2.0 * s.dD[0] / s.D[0] + 3.0 / 143.0 * (1.0 - om_a) / a0);
     return s;
 }
 
@@ -188,6 +195,8 @@ Schedule schedule_domega(double omega_m, double a_start, double a_stop, int n_st
     }
     d.D0 = (up.D0 - dn.D0) * inv;
     d.G0 = (up.G0 - dn.G0) * inv;
+    d.D20 = (up.D20 - dn.D20) * inv;
+    d.G20 = (up.G20 - dn.G20) * inv;
     return d;
 }
 

@@ -8,6 +8,8 @@
 // P = A k^n_s T^2 with A fixed by sigma_8 (top hat R = 8 Mpc/h).
 // Time stepping: kick/drift factors exact for linear growth (FastPM lineage,
 // cited by the pmwd paper via FastPM-vmad).
+// Second-order (2LPT) growth at a_0: D2 = -(3/7) D^2 Omega_m(a)^(-1/143)
+// (Bouchet et al. 1995 fit) and G2 = a^3 E dD2/da.
 #pragma once
 #include <vector>
 
@@ -32,6 +34,7 @@ struct Schedule {
     std::vector<double> a;          // a_n, n = 0..N
     std::vector<double> kick_a, drift, kick_b;   // n = 0..N-1
     double D0 = 0, G0 = 0;
+    double D20 = 0, G20 = 0;        // second-order growth D2, G2 at a_0
     std::vector<double> D, dD, G;   // at a_n
 };
 

@@ -175,15 +175,33 @@ void launch_recon_err(const uint32_t* a, const uint32_t* id, const uint32_t* b, 
 
 // Zel'dovich state from three real meshes s_j (pitch rp, on the particle
 // lattice): x = q + D0 s, p = G0 s in fixed point (xq, pq nullable), s_out
-// (nullable) = s.  launch_ic_check instead compares that state with the given
+// (nullable) = s; with s2v ([P][3] lattice order, 2LPT) the state adds D2 s2
+// and G2 s2.  launch_ic_check instead compares that state with the given
 // xq/pq: block partials of Sum|dx|^2 (cells^2), Sum|dp|^2 and Sum|p|^2 at
 // partials[0, nblocks, 2 nblocks) and max |dx| (cells) into *maxbits.
 void launch_ic_state(const float* smesh, long sStride, long rp, float D0, float G0,
                      const Lattice& L, uint32_t* xq, int32_t* pq, uint32_t* id, float* s_out,
-                     hipStream_t s);
+                     hipStream_t s, const float* s2v = nullptr, float D2 = 0.f, float G2 = 0.f);
 void launch_ic_check(const float* smesh, long sStride, long rp, float D0, float G0,
                      const Lattice& L, const uint32_t* xq, const int32_t* pq, const uint32_t* id,
-                     double* partials, int nblocks, unsigned* maxbits, hipStream_t s);
+                     double* partials, int nblocks, unsigned* maxbits, hipStream_t s,
+                     const float* s2v = nullptr, float D2 = 0.f, float G2 = 0.f);
+// 2LPT spectral multiplier on a half spectrum (integer wave numbers nv, m2 =
+// |n|^2, R = table[m2] or 1/m2 when table is null): mode 0 nv[a] nv[b] R (0 on
+// the Nyquist plane of a or b when a != b), mode 1 (m2 - nv[a]^2) R, mode 2
+// m2 table[m2]; times scale, 0 at m2 = 0.  dst = w src, or += when accumulate
+// (dst and src distinct).
+void launch_lpt_mul(const float2* src, float2* dst, int n, int cs, int ax_a, int ax_b, int mode,
+                    const float* table, float scale, bool accumulate, hipStream_t s);
+// Real meshes of one layout: op 0 out = ab + ac + bc; op 1 out = a - b^2 (- c^2
+// if c); op 2 out = scale a b.  out may alias a.
+void launch_lpt_pointwise(const float* a, const float* b, const float* c, float* out, int n,
+                          long rp, int op, float scale, hipStream_t s);
+// dst [n]^3 += scale * pitched src; block partials of Sum pitched src * b.
+void launch_add_from_pitched(const float* src, float* dst, int n, long rp, float scale,
+                             hipStream_t s);
+void launch_dot_pitched(const float* src, const float* b, int n, long rp, double* partials,
+                        int nblocks, hipStream_t s);
 // Compact [n]^3 <-> pitched rows.
 void launch_to_pitched(const float* src, float* dst, int n, long rp, float scale,
                        hipStream_t s);

@@ -661,21 +661,27 @@ k_recon_err(const uint32_t* __restrict__ a, const uint32_t* __restrict__ id,
     block_max_to(mx, maxbits);
 }
 
-// x = q + D0 s, p = G0 s in fixed point for lattice particle p.
-__device__ __forceinline__ void ic_fixed(const float s[3], const int jj[3], float D0, float G0,
+// x = q + D0 s (+ D2 s2), p = G0 s (+ G2 s2) in fixed point for lattice
+// particle p; s2 (the second-order field, 2LPT) is nullable.
+__device__ __forceinline__ void ic_fixed(const float s[3], const float* s2, const int jj[3],
+                                         float D0, float G0, float D2, float G2,
                                          const Lattice& L, uint32_t x[3], int32_t m[3]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        x[a] = (uint32_t)jj[a] * L.qstep +
-               (uint32_t)__float2ll_rn(__fmul_rn(__fmul_rn(D0, s[a]), L.len_to_pos));
-        m[a] = __float2int_rn(__fmul_rn(__fmul_rn(G0, s[a]), L.inv_mom_unit));
+        float dx = __fmul_rn(D0, s[a]), dp = __fmul_rn(G0, s[a]);
+        if (s2) {
+            dx = __fmaf_rn(D2, s2[a], dx);
+            dp = __fmaf_rn(G2, s2[a], dp);
+        }
+        x[a] = (uint32_t)jj[a] * L.qstep + (uint32_t)__float2ll_rn(__fmul_rn(dx, L.len_to_pos));
+        m[a] = __float2int_rn(__fmul_rn(dp, L.inv_mom_unit));
     }
 }
 
 __global__ void __launch_bounds__(kBlock)
 k_ic_state(const float* __restrict__ sm, long sStride, long rp, float D0, float G0, Lattice L,
            long P, uint32_t* __restrict__ xq, int32_t* __restrict__ pq, uint32_t* __restrict__ id,
-           float* __restrict__ s_out) {
+           float* __restrict__ s_out, const float* __restrict__ s2v, float D2, float G2) {
     for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
          p += (long)gridDim.x * kBlock) {
         int jj[3];
@@ -686,7 +692,7 @@ k_ic_state(const float* __restrict__ sm, long sStride, long rp, float D0, float 
         for (int a = 0; a < 3; ++a) s[a] = sm[a * sStride + o];
         uint32_t x[3];
         int32_t m[3];
-        ic_fixed(s, jj, D0, G0, L, x, m);
+        ic_fixed(s, s2v ? s2v + 3 * p : nullptr, jj, D0, G0, D2, G2, L, x, m);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             if (xq) xq[3 * p + a] = x[a];
@@ -700,21 +706,23 @@ k_ic_state(const float* __restrict__ sm, long sStride, long rp, float D0, float 
 __global__ void __launch_bounds__(kBlock)
 k_ic_check(const float* __restrict__ sm, long sStride, long rp, float D0, float G0, Lattice L,
            long P, const uint32_t* __restrict__ xq, const int32_t* __restrict__ pq,
-           const uint32_t* __restrict__ id, double* partials, unsigned* maxbits) {
+           const uint32_t* __restrict__ id, double* partials, unsigned* maxbits,
+           const float* __restrict__ s2v, float D2, float G2) {
     double ax = 0.0, ap = 0.0, aref = 0.0;
     float mx = 0.f;
     for (long p = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; p < P;
          p += (long)gridDim.x * kBlock) {
         // the state is in sorted order: compare with the ICs of lattice particle id[p]
         int jj[3];
-        lattice_index(id[p], L.np, jj);
+        const long lp = id[p];
+        lattice_index(lp, L.np, jj);
         const long o = mesh_row(jj[0], jj[1], L.np) * rp + jj[2];
         float s[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) s[a] = sm[a * sStride + o];
         uint32_t x[3];
         int32_t m[3];
-        ic_fixed(s, jj, D0, G0, L, x, m);
+        ic_fixed(s, s2v ? s2v + 3 * lp : nullptr, jj, D0, G0, D2, G2, L, x, m);
         float d2 = 0.f;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -734,6 +742,102 @@ k_ic_check(const float* __restrict__ sm, long sStride, long rp, float D0, float 
         partials[2 * gridDim.x + blockIdx.x] = s2;
     }
     block_max_to(mx, maxbits);
+}
+
+// ------------------------------------------------ 2LPT initial conditions
+
+// Spectral multiplier on a half spectrum [n][n][cs] (workspace row order) with
+// integer wave numbers nv = (n0, n1, n2) and m2 = |n|^2, R = table[m2] (or
+// 1/m2 without a table):
+//   mode 0  nv[a] nv[b] R          (a != b: 0 on the Nyquist plane of a or b)
+//   mode 1  (m2 - nv[a]^2) R       (sum of the two other diagonal entries)
+//   mode 2  m2 table[m2]
+// times scale, 0 at m2 = 0.  dst = w src, or dst += w src when accumulate.
+__global__ void __launch_bounds__(kBlock)
+k_lpt_mul(const float2* __restrict__ src, float2* __restrict__ dst, int n, int cs, int ax_a,
+          int ax_b, int mode, const float* __restrict__ table, float scale, int accumulate) {
+    const int h = n / 2 + 1;
+    const long N = (long)n * n * h;
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < N; i += (long)gridDim.x * kBlock) {
+        const int k2 = (int)(i % h);
+        const long row = i / h;
+        const int i1 = (int)(row % n), i0 = (int)(row / n);
+        const int nv[3] = {i0 < n / 2 ? i0 : i0 - n, i1 < n / 2 ? i1 : i1 - n, k2};
+        const bool nyq[3] = {i0 == n / 2, i1 == n / 2, k2 == n / 2};
+        const int m2 = nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2];
+        float w = 0.f;
+        if (m2 > 0) {
+            const float r = table ? table[m2] : 1.f / (float)m2;
+            if (mode == 0)
+                w = (ax_a != ax_b && (nyq[ax_a] || nyq[ax_b])) ? 0.f
+                                                               : (float)(nv[ax_a] * nv[ax_b]) * r;
+            else if (mode == 1)
+                w = (float)(m2 - nv[ax_a] * nv[ax_a]) * r;
+            else
+                w = (float)m2 * r;
+            w *= scale;
+        }
+        const long o = mesh_row(i0, i1, n) * cs + k2;
+        float2 v = src[o];
+        v.x *= w;
+        v.y *= w;
+        if (accumulate) {
+            const float2 d = dst[o];
+            v.x += d.x;
+            v.y += d.y;
+        }
+        dst[o] = v;
+    }
+}
+
+// Pointwise ops on real meshes of one layout (n^2 rows of pitch rp):
+//   op 0  out = a b + a c + b c
+//   op 1  out = a - b^2 (- c^2 when c is given)
+//   op 2  out = scale a b
+__global__ void __launch_bounds__(kBlock)
+k_lpt_pointwise(const float* a, const float* b, const float* c, float* out, int n, long rp,
+                int op, float scale) {
+    const long N = (long)n * n * n;
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < N; i += (long)gridDim.x * kBlock) {
+        const long o = (i / n) * rp + (i % n);
+        const float x = a[o], y = b[o];
+        float r;
+        if (op == 0) {
+            const float z = c[o];
+            r = x * y + x * z + y * z;
+        } else if (op == 1) {
+            r = x - y * y;
+            if (c) r -= c[o] * c[o];
+        } else {
+            r = scale * x * y;
+        }
+        out[o] = r;
+    }
+}
+
+// dst[i] += scale * pitched src (compact [n]^3 dst).
+__global__ void __launch_bounds__(kBlock)
+k_add_from_pitched(const float* __restrict__ src, float* __restrict__ dst, int n, long rp,
+                   float scale) {
+    const long N = (long)n * n * n;
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < N; i += (long)gridDim.x * kBlock) {
+        const long row = i / n;
+        dst[i] += scale * src[mesh_row((int)(row / n), (int)(row % n), n) * rp + (i % n)];
+    }
+}
+
+// Block partials of Sum_i pitched src_i * compact b_i.
+__global__ void __launch_bounds__(kBlock)
+k_dot_pitched(const float* __restrict__ src, const float* __restrict__ b, int n, long rp,
+              double* partials) {
+    const long N = (long)n * n * n;
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < N; i += (long)gridDim.x * kBlock) {
+        const long row = i / n;
+        acc += (double)src[mesh_row((int)(row / n), (int)(row % n), n) * rp + (i % n)] * b[i];
+    }
+    double s = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -1084,18 +1188,45 @@ void launch_recon_err(const uint32_t* a, const uint32_t* id, const uint32_t* b, 
 
 void launch_ic_state(const float* smesh, long sStride, long rp, float D0, float G0,
                      const Lattice& L, uint32_t* xq, int32_t* pq, uint32_t* id, float* s_out,
-                     hipStream_t s) {
+                     hipStream_t s, const float* s2v, float D2, float G2) {
     const long P = (long)L.np * L.np * L.np;
     hipLaunchKernelGGL(k_ic_state, dim3(grid_for(P)), dim3(kBlock), 0, s, smesh, sStride, rp, D0,
-                       G0, L, P, xq, pq, id, s_out);
+                       G0, L, P, xq, pq, id, s_out, s2v, D2, G2);
 }
 
 void launch_ic_check(const float* smesh, long sStride, long rp, float D0, float G0,
                      const Lattice& L, const uint32_t* xq, const int32_t* pq, const uint32_t* id,
-                     double* partials, int nblocks, unsigned* maxbits, hipStream_t s) {
+                     double* partials, int nblocks, unsigned* maxbits, hipStream_t s,
+                     const float* s2v, float D2, float G2) {
     const long P = (long)L.np * L.np * L.np;
     hipLaunchKernelGGL(k_ic_check, dim3(nblocks), dim3(kBlock), 0, s, smesh, sStride, rp, D0, G0,
-                       L, P, xq, pq, id, partials, maxbits);
+                       L, P, xq, pq, id, partials, maxbits, s2v, D2, G2);
+}
+
+void launch_lpt_mul(const float2* src, float2* dst, int n, int cs, int ax_a, int ax_b, int mode,
+                    const float* table, float scale, bool accumulate, hipStream_t s) {
+    const long N = (long)n * n * (n / 2 + 1);
+    hipLaunchKernelGGL(k_lpt_mul, dim3(grid_for(N)), dim3(kBlock), 0, s, src, dst, n, cs, ax_a,
+                       ax_b, mode, table, scale, accumulate ? 1 : 0);
+}
+
+void launch_lpt_pointwise(const float* a, const float* b, const float* c, float* out, int n,
+                          long rp, int op, float scale, hipStream_t s) {
+    const long N = (long)n * n * n;
+    hipLaunchKernelGGL(k_lpt_pointwise, dim3(grid_for(N)), dim3(kBlock), 0, s, a, b, c, out, n,
+                       rp, op, scale);
+}
+
+void launch_add_from_pitched(const float* src, float* dst, int n, long rp, float scale,
+                             hipStream_t s) {
+    const long N = (long)n * n * n;
+    hipLaunchKernelGGL(k_add_from_pitched, dim3(grid_for(N)), dim3(kBlock), 0, s, src, dst, n, rp,
+                       scale);
+}
+
+void launch_dot_pitched(const float* src, const float* b, int n, long rp, double* partials,
+                        int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot_pitched, dim3(nblocks), dim3(kBlock), 0, s, src, b, n, rp, partials);
 }
 
 void launch_to_pitched(const float* src, float* dst, int n, long rp, float scale,

@@ -61,7 +61,9 @@ int check_config(const pm_config* c, std::string* why) {
         *why = "too many checkpoints"; return PM_EINVAL;
     }
     if (c->filter != 0 && c->filter != 1) { *why = "filter must be 0 or 1"; return PM_EINVAL; }
-    if ((c->flags & ~(uint64_t)PM_F_TIMING) != 0) { *why = "unknown flags"; return PM_EINVAL; }
+    if ((c->flags & ~(uint64_t)(PM_F_TIMING | PM_F_2LPT)) != 0) {
+        *why = "unknown flags"; return PM_EINVAL;
+    }
     return PM_OK;
 }
 
@@ -89,7 +91,7 @@ struct Plan {
     size_t cplx, disp, mom, xi, pi, disp2, mom2, xi2, pi2, id, id2, fin_disp, fin_mom, s_ic, tmpv,
         noise, ckpt;
     size_t counts, offsets, keys, ranks, scan_tmp;
-    size_t radial_f, radial_ic, radial_ic_dom, losstab, tw, tw_stages, partials, sums, maxbits,
+    size_t radial_f, radial_ic, radial_ic_dom, radial_lpt, losstab, tw, tw_stages, partials, sums, maxbits,
         pkbins;
     size_t theta, gtheta, fbar, mlp_scratch;
     long cplx_elems, P, nkeys, ntab_f, ntab_p;
@@ -138,6 +140,7 @@ struct Plan {
         radial_f = take(ntab_f * sizeof(float));
         radial_ic = take(ntab_p * sizeof(float));
         radial_ic_dom = take(ntab_p * sizeof(float));
+        radial_lpt = take(ntab_p * sizeof(float));
         losstab = take(ntab_f * sizeof(float));
         tw = take((size_t)ng * sizeof(float2));
         tw_stages = take(kStageTableSize * sizeof(float2));
@@ -176,7 +179,7 @@ struct pm_ctx {
     uint32_t *fin_x, *ckpt;        // final state and checkpoints, lattice order
     int32_t* fin_p;
     float *s_ic, *tmpv, *noise;
-    float *radial_f, *radial_ic, *radial_ic_dom, *theta, *gtheta, *fbar, *mlp_scratch;
+    float *radial_f, *radial_ic, *radial_ic_dom, *radial_lpt, *theta, *gtheta, *fbar, *mlp_scratch;
     float* losstab;                    // radial cotangent table of pm_loss_pk
     std::vector<float> losstab_host;   // its host copy (kept alive across the async upload)
     float2* tw;
@@ -227,6 +230,7 @@ struct pm_ctx {
         return PM_OK;
     }
     float* creal(int k) { return reinterpret_cast<float*>(C[k]); }
+    bool lpt2() const { return (cfg.flags & PM_F_2LPT) != 0; }
     long creal_stride() const { return 2 * plan.cplx_elems; }
     float mass() const { return (float)(lat.ratio * lat.ratio * lat.ratio); }
 };
@@ -276,8 +280,10 @@ int upload_tables(pm_ctx* ctx) {
     std::vector<double> dpk = pk_table_domega(co, c.box, (int)(ntp - 1));
     const double vcell = std::pow(c.box / np, 3.0);
     const double norm_p = c.box / (2.0 * kPi) / ((double)np * np * np);
-    std::vector<float> ric(ntp), ricd(ntp), rf(ntf);
+    std::vector<float> ric(ntp), ricd(ntp), rlpt(ntp), rf(ntf);
     for (long n2 = 0; n2 < ntp; ++n2) {
+        // second-order displacement s2_k = -i k S_k / k^2 (with the 1/Np^3 of the inverse)
+        rlpt[n2] = n2 == 0 ? 0.f : (float)(-norm_p / n2);
         if (n2 == 0 || pk[n2] <= 0.0) {
             ric[n2] = 0.f;
             ricd[n2] = 0.f;
@@ -301,6 +307,7 @@ int upload_tables(pm_ctx* ctx) {
     hipStream_t s = ctx->stream;
     if (hipMemcpyAsync(ctx->radial_ic, ric.data(), ntp * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(ctx->radial_ic_dom, ricd.data(), ntp * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(ctx->radial_lpt, rlpt.data(), ntp * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(ctx->radial_f, rf.data(), ntf * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(ctx->tw, tw.data(), ng * sizeof(float2), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(ctx->tw_stages, stages.data(), kStageTableSize * sizeof(float2),
@@ -399,42 +406,135 @@ void vjp_mesh(pm_ctx* ctx, const uint32_t* xq, const float* v, float coeff, doub
     { KTimer t(ctx, PM_K_FFT_X, r + c); launch_fft_x_c2r(ctx->C[0], ng, cs, 1, cst, ctx->twd, s); }
 }
 
-// Zel'dovich displacement (a = 1) of the stored noise with the radial table;
-// leaves s_j as real meshes in C1..C3 (particle-grid geometry) and writes
-// s_out [P][3] and the fixed-point state x = q + D0 s, p = G0 s (each nullable).
-void ic_synthesis(pm_ctx* ctx, const float* radial, float* s_out, uint32_t* xq, int32_t* pq,
-                  uint32_t* id) {
+// Gradient synthesis on the particle lattice: the real mesh in C0 becomes
+// s_j = IDFT(i n_j radial(|n|^2) DFT(C0)) in C1..C3 (the force chain; radial
+// carries the 1/k^2, the k units and the 1/Np^3 of the inverse).
+void grad_synthesis(pm_ctx* ctx, const float* radial) {
     hipStream_t s = ctx->stream;
-    const int np = ctx->np, cs = ctx->cs_p, ng = ctx->ng;
+    const int np = ctx->np, cs = ctx->cs_p;
     const long cst = ctx->plan.cplx_elems;
-    const long rp = 2L * cs;
-    KTimer t(ctx, PM_K_OTHER, 0);
-    launch_to_pitched(ctx->noise, ctx->creal(0), np, rp, 1.f, s);
     launch_fft_x_r2c(ctx->C[0], np, cs, 1, cst, ctx->twd, s);
     launch_fft_axis(ctx->C[0], np, cs, 1, -1, 1, cst, ctx->twd, s);
     launch_grad_z(ctx->C[0], ctx->C[1], cst, np, cs, radial, ctx->twd, s);
     launch_fft_axis(ctx->C[1], np, cs, 1, 1, 1, cst, ctx->twd, s);
     launch_fft_y_split(ctx->C[2], ctx->C[3], np, cs, ctx->twd, s);
     launch_fft_x_c2r_dk2(ctx->C[1], np, cs, 3, cst, 2, ctx->twd, s);
+}
+
+// Transpose of grad_synthesis: the real mesh Sum_j IDFT(conj(i n_j radial)
+// DFT(v_j)) of v [P][3] (lattice order) in C0.
+void grad_transpose(pm_ctx* ctx, const float* v, const float* radial) {
+    hipStream_t s = ctx->stream;
+    const int np = ctx->np, cs = ctx->cs_p;
+    const long cst = ctx->plan.cplx_elems;
+    const long rp = 2L * cs;
+    launch_deinterleave(v, ctx->creal(1), ctx->creal_stride(), np, rp, s);
+    launch_fft_x_r2c(ctx->C[1], np, cs, 3, cst, ctx->twd, s);
+    launch_fft_axis(ctx->C[1], np, cs, 1, -1, 3, cst, ctx->twd, s);
+    launch_grad_adj_z(ctx->C[1], cst, ctx->C[0], ctx->C[0], np, cs, radial, nullptr, 0.f,
+                      ctx->twd, s);
+    launch_fft_axis(ctx->C[0], np, cs, 1, 1, 1, cst, ctx->twd, s);
+    launch_fft_x_c2r(ctx->C[0], np, cs, 1, cst, ctx->twd, s);
+}
+
+// Zel'dovich displacement (a = 1) of white noise `noise` [Np^3] with the radial
+// table; leaves s_j as real meshes in C1..C3 (particle-grid geometry) and writes
+// s_out [P][3] and the fixed-point state x = q + D0 s, p = G0 s (each nullable).
+// With s2v ([P][3] lattice order, 2LPT) the state adds D2 s2 and G2 s2.
+void ic_synthesis(pm_ctx* ctx, const float* noise, const float* radial, float* s_out,
+                  uint32_t* xq, int32_t* pq, uint32_t* id, const float* s2v = nullptr) {
+    hipStream_t s = ctx->stream;
+    const long rp = 2L * ctx->cs_p;
+    KTimer t(ctx, PM_K_OTHER, 0);
+    launch_to_pitched(noise, ctx->creal(0), ctx->np, rp, 1.f, s);
+    grad_synthesis(ctx, radial);
     launch_ic_state(ctx->creal(1), ctx->creal_stride(), rp, (float)ctx->sched.D0,
-                    (float)ctx->sched.G0, ctx->lat, xq, pq, id, s_out, s);
+                    (float)ctx->sched.G0, ctx->lat, xq, pq, id, s_out, s, s2v,
+                    (float)ctx->sched.D20, (float)ctx->sched.G20);
 }
 
 // dL/dnoise = transpose of the Zel'dovich synthesis applied to s_bar [P][3].
 void ic_transpose(pm_ctx* ctx, const float* s_bar, float* g_noise) {
-    hipStream_t s = ctx->stream;
-    const int np = ctx->np, cs = ctx->cs_p, ng = ctx->ng;
-    const long cst = ctx->plan.cplx_elems;
-    const long rp = 2L * cs;
     KTimer t(ctx, PM_K_OTHER, 0);
-    launch_deinterleave(s_bar, ctx->creal(1), ctx->creal_stride(), np, rp, s);
-    launch_fft_x_r2c(ctx->C[1], np, cs, 3, cst, ctx->twd, s);
-    launch_fft_axis(ctx->C[1], np, cs, 1, -1, 3, cst, ctx->twd, s);
-    launch_grad_adj_z(ctx->C[1], cst, ctx->C[0], ctx->C[0], np, cs, ctx->radial_ic, nullptr, 0.f,
-                      ctx->twd, s);
-    launch_fft_axis(ctx->C[0], np, cs, 1, 1, 1, cst, ctx->twd, s);
-    launch_fft_x_c2r(ctx->C[0], np, cs, 1, cst, ctx->twd, s);
-    launch_from_pitched(ctx->creal(0), g_noise, np, rp, s);
+    grad_transpose(ctx, s_bar, ctx->radial_ic);
+    launch_from_pitched(ctx->creal(0), g_noise, ctx->np, 2L * ctx->cs_p, ctx->stream);
+}
+
+// The six Hessian entries (a, b), a <= b, of the potential of the linear density.
+constexpr int kPairs[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+
+// Second-order (2LPT) displacement at a = 1 of white noise `noise` [Np^3]:
+// Hessian entries phi_ab = IDFT(k_a k_b sqrt(P/V_c) noise_k / k^2) (the
+// off-diagonal ones zero on the Nyquist planes of a and b), source
+// S = Sum_{a<b} (phi_aa phi_bb - phi_ab^2), s2_k = -i k S_k / k^2 (the gradient's
+// own Nyquist rule).  Writes s2_out [P][3] in lattice order; uses C0..C3.
+void lpt_second_order(pm_ctx* ctx, const float* noise, float* s2_out) {
+    hipStream_t s = ctx->stream;
+    const int np = ctx->np, cs = ctx->cs_p;
+    const long cst = ctx->plan.cplx_elems, rp = 2L * cs;
+    // radial_ic holds sqrt(P/V_c) (L/2pi) / (Np^3 |n|^2): times 2pi/L and n_a n_b
+    // it is the Hessian multiplier including the 1/Np^3 of the inverse
+    const float kf = (float)(2.0 * kPi / ctx->cfg.box);
+    float *r0 = ctx->creal(0), *r1 = ctx->creal(1), *r2 = ctx->creal(2), *r3 = ctx->creal(3);
+    KTimer t(ctx, PM_K_OTHER, 0);
+    launch_to_pitched(noise, r0, np, rp, 1.f, s);
+    launch_fft3_r2c(ctx->C[0], np, cs, 1, cst, ctx->twd, s);
+    for (int a = 0; a < 3; ++a)
+        launch_lpt_mul(ctx->C[0], ctx->C[1 + a], np, cs, a, a, 0, ctx->radial_ic, kf, false, s);
+    launch_fft3_c2r(ctx->C[1], np, cs, 3, cst, ctx->twd, s);
+    launch_lpt_pointwise(r1, r2, r3, r1, np, rp, 0, 1.f, s);
+    launch_lpt_mul(ctx->C[0], ctx->C[2], np, cs, 0, 1, 0, ctx->radial_ic, kf, false, s);
+    launch_lpt_mul(ctx->C[0], ctx->C[3], np, cs, 0, 2, 0, ctx->radial_ic, kf, false, s);
+    launch_fft3_c2r(ctx->C[2], np, cs, 2, cst, ctx->twd, s);
+    launch_lpt_pointwise(r1, r2, r3, r1, np, rp, 1, 1.f, s);
+    launch_lpt_mul(ctx->C[0], ctx->C[2], np, cs, 1, 2, 0, ctx->radial_ic, kf, false, s);
+    launch_fft3_c2r(ctx->C[2], np, cs, 1, cst, ctx->twd, s);
+    launch_lpt_pointwise(r1, r2, nullptr, r0, np, rp, 1, 1.f, s);   // S in C0
+    grad_synthesis(ctx, ctx->radial_lpt);
+    launch_ic_state(r1, ctx->creal_stride(), rp, 0.f, 0.f, ctx->lat, nullptr, nullptr, nullptr,
+                    s2_out, s);
+}
+
+// Transpose of lpt_second_order at `noise`: g_noise [Np^3] += its transpose
+// applied to s2_bar [P][3] (lattice order), and sums[slot] = the Omega_m
+// derivative of <s2_bar, s2> through sqrt(P/V_c).  Reverse mode through the
+// source: S_bar = transpose of the s2 gradient, phi_aa_bar = S_bar (phi_bb +
+// phi_cc) over the two other axes, phi_ab_bar = -2 S_bar phi_ab; each Hessian
+// entry is a real even multiplier of the noise, so its transpose is itself.
+int lpt_second_order_transpose(pm_ctx* ctx, const float* noise, const float* s2_bar,
+                               float* g_noise, int slot, int nb) {
+    hipStream_t s = ctx->stream;
+    const int np = ctx->np, cs = ctx->cs_p;
+    const long cst = ctx->plan.cplx_elems, rp = 2L * cs;
+    const float kf = (float)(2.0 * kPi / ctx->cfg.box);
+    float *r0 = ctx->creal(0), *r2 = ctx->creal(2), *r3 = ctx->creal(3);
+    KTimer t(ctx, PM_K_OTHER, 0);
+    grad_transpose(ctx, s2_bar, ctx->radial_lpt);
+    if (hipMemcpyAsync(r3, r0, (size_t)np * np * rp * sizeof(float), hipMemcpyDeviceToDevice, s) !=
+        hipSuccess)
+        return ctx->fail(PM_EHIP, "device copy failed");
+    launch_to_pitched(noise, r0, np, rp, 1.f, s);
+    launch_fft3_r2c(ctx->C[0], np, cs, 1, cst, ctx->twd, s);
+    // C1 = Sum_ab (n_a n_b / |n|^2) DFT(phi_ab_bar)
+    for (int k = 0; k < 6; ++k) {
+        const int a = kPairs[k][0], b = kPairs[k][1];
+        launch_lpt_mul(ctx->C[0], ctx->C[2], np, cs, a, b, a == b ? 1 : 0, ctx->radial_ic, kf,
+                       false, s);
+        launch_fft3_c2r(ctx->C[2], np, cs, 1, cst, ctx->twd, s);
+        launch_lpt_pointwise(r2, r3, nullptr, r2, np, rp, 2, a == b ? 1.f : -2.f, s);
+        launch_fft3_r2c(ctx->C[2], np, cs, 1, cst, ctx->twd, s);
+        launch_lpt_mul(ctx->C[2], ctx->C[1], np, cs, a, b, 0, nullptr, 1.f, k > 0, s);
+    }
+    // Omega_m: < IDFT(d sqrt(P/V_c)/dOmega_m C1), noise >
+    launch_lpt_mul(ctx->C[1], ctx->C[2], np, cs, 0, 0, 2, ctx->radial_ic_dom, kf, false, s);
+    launch_fft3_c2r(ctx->C[2], np, cs, 1, cst, ctx->twd, s);
+    launch_dot_pitched(r2, noise, np, rp, ctx->partials, nb, s);
+    launch_reduce(ctx->partials, nb, ctx->sums, slot, s);
+    // noise: IDFT(sqrt(P/V_c) C1)
+    launch_lpt_mul(ctx->C[1], ctx->C[2], np, cs, 0, 0, 2, ctx->radial_ic, kf, false, s);
+    launch_fft3_c2r(ctx->C[2], np, cs, 1, cst, ctx->twd, s);
+    launch_add_from_pitched(r2, g_noise, np, rp, 1.f, s);
+    return PM_OK;
 }
 
 int copy_d2d(pm_ctx* ctx, void* dst, const void* src, size_t bytes) {
@@ -503,6 +603,28 @@ int pm_host_tables(const pm_config* cfg, const pm_cosmology* cosmo, double* coef
     return PM_OK;
 }
 
+int pm_lpt2_growth(const pm_config* cfg, const pm_cosmology* cosmo, double* out) {
+    std::string why;
+    int rc = check_config(cfg, &why);
+    if (rc == PM_OK) rc = check_cosmo(cosmo, &why);
+    if (rc == PM_OK && !out) {
+        why = "out is required";
+        rc = PM_EINVAL;
+    }
+    if (rc != PM_OK) {
+        g_err = why;
+        return rc;
+    }
+    const double om = to_cosmo(cosmo).omega_m;
+    Schedule s = schedule(om, cfg->a_start, cfg->a_stop, cfg->n_steps);
+    Schedule d = schedule_domega(om, cfg->a_start, cfg->a_stop, cfg->n_steps);
+    out[0] = s.D20;
+    out[1] = s.G20;
+    out[2] = d.D20;
+    out[3] = d.G20;
+    return PM_OK;
+}
+
 int pm_init(const pm_config* cfg, const pm_cosmology* cosmo, void* workspace, size_t ws_bytes,
             void* hip_stream, pm_ctx** out) {
     std::string why;
@@ -555,6 +677,7 @@ int pm_init(const pm_config* cfg, const pm_cosmology* cosmo, void* workspace, si
     ctx->radial_f = ctx->at<float>(p.radial_f);
     ctx->radial_ic = ctx->at<float>(p.radial_ic);
     ctx->radial_ic_dom = ctx->at<float>(p.radial_ic_dom);
+    ctx->radial_lpt = ctx->at<float>(p.radial_lpt);
     ctx->losstab = ctx->at<float>(p.losstab);
     ctx->tw = ctx->at<float2>(p.tw);
     ctx->tw_stages = ctx->at<float2>(p.tw_stages);
@@ -653,7 +776,9 @@ int pm_forward(pm_ctx* ctx, const float* noise, float* disp_out, float* mom_out,
     const int N = c.n_steps;
     (void)hipEventRecord(ctx->ev[0], s);
     PM_TRY(copy_d2d(ctx, ctx->noise, noise, (size_t)ctx->P * sizeof(float)));
-    ic_synthesis(ctx, ctx->radial_ic, ctx->s_ic, ctx->xq, ctx->pq, ctx->id);
+    if (ctx->lpt2()) lpt_second_order(ctx, ctx->noise, ctx->tmpv);
+    ic_synthesis(ctx, ctx->noise, ctx->radial_ic, ctx->s_ic, ctx->xq, ctx->pq, ctx->id,
+                 ctx->lpt2() ? ctx->tmpv : nullptr);
     for (int n = 0; n <= N; ++n) {
         compute_force(ctx, sc.a[n], false);
         const double kick = (n > 0 ? sc.kick_b[n - 1] : 0.0) + (n < N ? sc.kick_a[n] : 0.0);
@@ -702,7 +827,10 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
     const int nb = std::min(particle_blocks(P), 4096);
     const int slotS = 0, slotD = N + 1, slotX = 2 * N + 1;   // S_m, D_n, extras
     const int xD0 = slotX, xG0 = slotX + 1, xSig = slotX + 2, xOm = slotX + 3,
-              xIc = slotX + 4, xIcMom = slotX + 5, xIcMomRef = slotX + 6, xCk = slotX + 8;
+              xIc = slotX + 4, xIcMom = slotX + 5, xIcMomRef = slotX + 6, xCk = slotX + 8,
+              xD20 = xCk + PM_MAX_CHECKPOINTS, xG20 = xD20 + 1, xSig2 = xD20 + 2,
+              xOm2 = xD20 + 3;
+    const bool lpt2 = ctx->lpt2();
     const float mass = ctx->mass();
     const double bytes_unkick = 72.0 * P + 3 * mesh_r(ctx->ng);
     const double bytes_wgrad = 84.0 * P + mesh_r(ctx->ng);
@@ -780,13 +908,16 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
                      ctx->lat, ctx->bins, 0.f, 2, nullptr, s);
     }
 
-    // ICs: x_0 = q + D0 s, p_0 = G0 s.  Reconstruction check against the ICs.
-    ic_synthesis(ctx, ctx->radial_ic, ctx->s_ic, nullptr, nullptr, nullptr);
+    // ICs: x_0 = q + D0 s (+ D20 s2), p_0 = G0 s (+ G20 s2).  Reconstruction
+    // check against the ICs.  2LPT: s2 in pi_alt (lattice order; free here).
+    if (lpt2) lpt_second_order(ctx, ctx->noise, ctx->pi_alt);
+    ic_synthesis(ctx, ctx->noise, ctx->radial_ic, ctx->s_ic, nullptr, nullptr, nullptr);
     {
         KTimer t(ctx, PM_K_OTHER, 0);
         launch_ic_check(ctx->creal(1), ctx->creal_stride(), 2L * ctx->cs_p, (float)sc.D0,
                         (float)sc.G0, ctx->lat, ctx->xq, ctx->pq, ctx->id, ctx->partials, nb,
-                        ctx->maxbits, s);
+                        ctx->maxbits, s, lpt2 ? ctx->pi_alt : nullptr, (float)sc.D20,
+                        (float)sc.G20);
         launch_reduce(ctx->partials, nb, ctx->sums, xIc, s);
         launch_reduce(ctx->partials + nb, nb, ctx->sums, xIcMom, s);
         launch_reduce(ctx->partials + 2 * nb, nb, ctx->sums, xIcMomRef, s);
@@ -798,10 +929,22 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
         launch_axpby_scatter(ctx->tmpv, ctx->xi, (float)sc.D0, ctx->pi, (float)sc.G0, ctx->id, P, s);
         launch_dot3(ctx->tmpv, ctx->s_ic, P, ctx->partials, nb, s);
         launch_reduce(ctx->partials, nb, ctx->sums, xSig, s);
+        if (lpt2) {
+            launch_dot3(ctx->xi, ctx->pi_alt, P, ctx->partials, nb, s, ctx->id);
+            launch_reduce(ctx->partials, nb, ctx->sums, xD20, s);
+            launch_dot3(ctx->pi, ctx->pi_alt, P, ctx->partials, nb, s, ctx->id);
+            launch_reduce(ctx->partials, nb, ctx->sums, xG20, s);
+            // s2_bar = D20 xi + G20 pi, in lattice order
+            launch_axpby_scatter(ctx->xi_alt, ctx->xi, (float)sc.D20, ctx->pi, (float)sc.G20,
+                                 ctx->id, P, s);
+            launch_dot3(ctx->xi_alt, ctx->pi_alt, P, ctx->partials, nb, s);
+            launch_reduce(ctx->partials, nb, ctx->sums, xSig2, s);
+        }
     }
     ic_transpose(ctx, ctx->tmpv, g_noise);
+    if (lpt2) PM_TRY(lpt_second_order_transpose(ctx, ctx->noise, ctx->xi_alt, g_noise, xOm2, nb));
     // Omega_m dependence of P(k): s' = synthesis with d radial / d Omega_m
-    ic_synthesis(ctx, ctx->radial_ic_dom, ctx->xi_alt, nullptr, nullptr, nullptr);
+    ic_synthesis(ctx, ctx->noise, ctx->radial_ic_dom, ctx->xi_alt, nullptr, nullptr, nullptr);
     {
         KTimer t(ctx, PM_K_OTHER, 0);
         launch_dot3(ctx->tmpv, ctx->xi_alt, P, ctx->partials, nb, s);
@@ -824,7 +967,9 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
     for (int n = 0; n < N; ++n)
         g_om += h[slotS + n] * d.kick_a[n] + h[slotS + n + 1] * d.kick_b[n] + h[slotD + n] * d.drift[n];
     g_om += h[xD0] * d.D0 + h[xG0] * d.G0 + h[xOm];
-    const double g_s8 = h[xSig] / ctx->cosmo.sigma8;
+    // 2LPT: s2 ~ sigma_8^2, hence the factor 2 (the slots stay 0 otherwise)
+    g_om += h[xD20] * d.D20 + h[xG20] * d.G20 + h[xOm2];
+    const double g_s8 = (h[xSig] + 2.0 * h[xSig2]) / ctx->cosmo.sigma8;
     for (double v : h)
         if (!std::isfinite(v)) return ctx->fail(PM_ENUMERIC, "non-finite adjoint sum");
     if (g_cosmo) {
@@ -845,6 +990,19 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
     ctx->stats.ic_max_cells = as_float(mb[0]);
     ctx->stats.ic_mom_rel_rms = h[xIcMomRef] > 0 ? std::sqrt(h[xIcMom] / h[xIcMomRef]) : 0.0;
     return PM_OK;
+}
+
+int pm_initial_conditions(pm_ctx* ctx, const float* noise, float* disp_out, float* mom_out) {
+    PM_TRY(ctx_check(ctx));
+    if (!noise || !disp_out || !mom_out) return ctx->fail(PM_EINVAL, "noise, disp and mom are required");
+    if (ctx->lpt2()) lpt_second_order(ctx, noise, ctx->tmpv);
+    ic_synthesis(ctx, noise, ctx->radial_ic, ctx->s_ic, ctx->xq, ctx->pq, ctx->id,
+                 ctx->lpt2() ? ctx->tmpv : nullptr);
+    {
+        KTimer t(ctx, PM_K_OTHER, 0);
+        launch_from_fixed(ctx->xq, ctx->pq, ctx->id, ctx->lat, disp_out, mom_out, ctx->stream);
+    }
+    return ctx->hip_check("pm_initial_conditions");
 }
 
 int pm_loss_mse(pm_ctx* ctx, const float* dens, const float* target, float* g_dens,

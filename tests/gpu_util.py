@@ -20,9 +20,9 @@ def host(t):
 
 
 @functools.lru_cache(maxsize=None)
-def context(ptcl_grid, mesh, box, n_steps, checkpoint_every=0, filter=False):
+def context(ptcl_grid, mesh, box, n_steps, checkpoint_every=0, filter=False, lpt_order=1):
     cfg = api.make_config(ptcl_grid, mesh, box, n_steps, checkpoint_every=checkpoint_every,
-                          filter=filter)
+                          filter=filter, lpt_order=lpt_order)
     return api.PMContext(cfg, CO)
 
 
@@ -30,8 +30,8 @@ def ctx_for(w: Workload, **kw):
     return context(w.ptcl_grid, w.mesh, w.box, w.n_steps, **kw)
 
 
-def setup_for(w: Workload):
-    return opm.Setup(w.ptcl_grid, w.mesh, w.box, w.n_steps, CO, w.a_start, w.a_stop)
+def setup_for(w: Workload, lpt_order=1):
+    return opm.Setup(w.ptcl_grid, w.mesh, w.box, w.n_steps, CO, w.a_start, w.a_stop, lpt_order)
 
 
 def rel_l2(a, b):

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 @pytest.mark.parametrize("field,value", [("ptcl_grid", 48), ("mesh", 12), ("mesh", 2048),
                                          ("box", -1.0), ("n_steps", 0), ("a_start", 0.0),
-                                         ("filter", 2), ("flags", 2), ("checkpoint_every", -1)])
+                                         ("filter", 2), ("flags", 4), ("checkpoint_every", -1)])
 def test_invalid_config_rejected_on_host(field, value):
     cfg = api.config_from_workload(SMALL)
     setattr(cfg, field, value)
@@ -92,3 +92,21 @@ def test_host_tables_match_oracle(w):
     ref = C.linear_pk(2 * np.pi / w.box * np.sqrt(nsq), CO)
     np.testing.assert_allclose(t["pk"][1:], ref[1:], rtol=1e-9)
     assert t["pk"][0] == 0.0
+
+
+@pytest.mark.parametrize("w", [SMALL, MEDIUM])
+def test_lpt2_growth_matches_oracle(w):
+    cfg = api.config_from_workload(w)
+    g = api.lpt2_growth(cfg, CO)
+    co = C.kdk_coefficients(CO.omega_m, w.a_start, w.a_stop, w.n_steps)
+    d = C.kdk_coefficient_derivatives(CO.omega_m, w.a_start, w.a_stop, w.n_steps)
+    assert abs(g["D2"] / co.D20 - 1) < 1e-11 and abs(g["G2"] / co.G20 - 1) < 1e-10
+    assert abs(g["d_D2"] / d.D20 - 1) < 1e-6 and abs(g["d_G2"] / d.G20 - 1) < 1e-6
+    assert g["D2"] < 0 and g["G2"] < 0
+
+
+def test_lpt_order_sets_the_flag():
+    assert api.make_config(32, 64, 64.0, 10, lpt_order=2).flags == _lib.PM_F_2LPT
+    assert api.make_config(32, 64, 64.0, 10).flags == 0
+    with pytest.raises(ValueError):
+        api.make_config(32, 64, 64.0, 10, lpt_order=3)
