@@ -49,6 +49,8 @@ def parse():
     p.add_argument("--no-learned", action="store_true",
                    help="skip the learned-filter 512^3-mesh vs plain 1024^3-mesh comparison")
     p.add_argument("--weights", default=WEIGHTS, help="trained filter weights (.npy)")
+    p.add_argument("--no-lpt2", action="store_true",
+                   help="skip the run from second-order (2LPT) initial conditions")
     p.add_argument("--cpu-only", action="store_true", help="only the oracle CPU baseline")
     p.add_argument("--calib-copy-gib", type=float, default=0.0,
                    help="also run one device copy of this many GiB (HBM counter calibration)")
@@ -221,6 +223,10 @@ def main():
         out["pure_reverse"] = {"value": P * w.n_steps / dtp, "ms_per_step": dtp * 1e3,
                                "ic_rms_cells": sp["ic_rms_cells"],
                                "ic_max_cells": sp["ic_max_cells"]}
+    if not args.no_lpt2:
+        pm = pure = None
+        torch.cuda.empty_cache()
+        out["lpt2"] = lpt2_leg(args, w, co, noise, target, fams, make)
     if not args.no_learned and os.path.exists(args.weights) and w.name == "pm-512p-1024m-63s":
         pm = pure = None   # release the 1024^3 workspaces
         torch.cuda.empty_cache()
@@ -228,6 +234,51 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
+
+
+def lpt2_leg(args, w, co, noise, target, plain_fams, make):
+    """The same forward + adjoint run from 2LPT initial conditions: whole-run
+    rate, the extra initial-condition time (the "other" kernel family holds the
+    ICs, their adjoint and the reconstruction checks) and the time of the
+    initial conditions alone, Zel'dovich vs 2LPT (HIP events, 5 calls each)."""
+    import torch
+
+    from paper_2211_09958_amd import api
+    P = w.ptcl_grid ** 3
+    cfg = api.config_from_workload(w, checkpoint_every=args.checkpoint_every, timing=True)
+    cfg.flags |= api._lib.PM_F_2LPT
+    pm = api.PMContext(cfg, co, device="cuda:0")
+
+    def run():
+        disp, mom, dens = pm.forward(noise)
+        _, g = pm.loss_mse(dens, target)
+        return pm.adjoint(g_dens=g)[1]
+
+    run()
+    torch.cuda.synchronize()
+    pm.reset_stats()
+    t0 = time.perf_counter()
+    g_cosmo = run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = pm.stats()
+    other = st["kernels"].get("other", {}).get("ms", 0.0)
+    plain_other = plain_fams.get("other", {}).get("ms", 0.0) / args.steps
+    ic_ms = {}
+    for name, ctx in (("zeldovich", make(args.checkpoint_every)), ("2lpt", pm)):
+        ctx.initial_conditions(noise)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            ctx.initial_conditions(noise)
+        e1.record()
+        torch.cuda.synchronize()
+        ic_ms[name] = e0.elapsed_time(e1) / 5
+        del ctx
+    return {"value": P * w.n_steps / dt, "unit": "particle-steps/s", "ms_per_run": dt * 1e3,
+            "other_family_ms_per_run": other, "plain_other_family_ms_per_run": plain_other,
+            "initial_conditions_ms": ic_ms, "ic_max_cells": st["ic_max_cells"],
+            "ic_mom_rel_rms": st["ic_mom_rel_rms"], "grad_cosmo": list(g_cosmo)}
 
 
 def learned_vs_plain(args, co, noise, disp_plain, plain_value):
