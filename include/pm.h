@@ -172,6 +172,20 @@ int pm_set_cosmology(pm_ctx* ctx, const pm_cosmology* cosmo);
  * forward run. */
 int pm_set_filter(pm_ctx* ctx, const float* weights_dev);
 
+/* Per-step scales of the time integration (the temporal counterpart of the
+ * learned force filter: the paper names spatiotemporal optimization of the PM
+ * solver as its follow-up; a schedule correction trained through the adjoint).
+ * scales_host [3*n_steps] multiplies kick_a[0..N-1] | drift[0..N-1] |
+ * kick_b[0..N-1] of pm_host_tables (and their Omega_m derivatives); all ones,
+ * the default, is plain KDK.  Finite values only.  Reverse-time reconstruction
+ * stays exact for any scales.  Invalidates the stored forward run. */
+int pm_set_step_scales(pm_ctx* ctx, const double* scales_host);
+
+/* dL/d(scales) [3*n_steps] (same layout) of the last pm_adjoint, i.e. the
+ * unscaled factor times dL/d(factor) per step.  PM_ESTATE when no pm_adjoint
+ * followed the last pm_forward. */
+int pm_step_gradients(pm_ctx* ctx, double* out_host);
+
 /* Forward simulation.
  *   noise_dev [Np][Np][Np]  unit white noise; the Zel'dovich ICs are
  *            x_0 = q + D(a_0) s, p_0 = G(a_0) s with

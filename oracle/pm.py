@@ -22,7 +22,9 @@ s_k = i k delta_k / k^2, and x_0 = q + D(a_0) s, p_0 = G(a_0) s.  With
 x_0 = q + D s + D2 s2, p_0 = G s + G2 s2.
 
 Time stepping is kick-drift-kick with growth-factor coefficients
-(``cosmology.kdk_coefficients``):
+(``cosmology.kdk_coefficients``), each optionally multiplied by a per-step
+scale (``Setup.step_scales``, the temporal counterpart of the learned force
+filter: a correction of the time integration trained through the adjoint):
     F_0 = F(x_0)
     for n = 0 .. N-1:
         p <- p + kick_a_n F_n ;  x <- x + drift_n p ;
@@ -50,6 +52,7 @@ class Setup:
     a_start: float = 1.0 / 64
     a_stop: float = 1.0
     lpt_order: int = 1            # 1: Zel'dovich ICs; 2: plus the 2LPT term
+    step_scales: object = None    # [3, N] multipliers of kick_a, drift, kick_b (None: 1)
 
     @property
     def n_particles(self):
@@ -64,6 +67,17 @@ def setup_from(workload, cosmo=None):
     return Setup(workload.ptcl_grid, workload.mesh, workload.box, workload.n_steps,
                  cosmo if cosmo is not None else workload.cosmo,
                  workload.a_start, workload.a_stop)
+
+
+def step_coefficients(setup):
+    """KDK factors of ``setup`` with the per-step scales applied (D0, G0, D20
+    and G20 unscaled)."""
+    co = cosmo_mod.kdk_coefficients(setup.cosmo.omega_m, setup.a_start, setup.a_stop,
+                                    setup.n_steps)
+    if setup.step_scales is not None:
+        sc = np.asarray(setup.step_scales, dtype=np.float64).reshape(3, setup.n_steps)
+        co.kick_a, co.drift, co.kick_b = co.kick_a * sc[0], co.drift * sc[1], co.kick_b * sc[2]
+    return co
 
 
 def lattice(ptcl_grid, box):
@@ -186,8 +200,7 @@ def forward(noise, setup, theta=None):
 
 def initial_state(s, setup, s2=None):
     """(x_0 - q, p_0) = (D s + D2 s2, G s + G2 s2) at a_0 (s2 term for 2LPT)."""
-    co = cosmo_mod.kdk_coefficients(setup.cosmo.omega_m, setup.a_start, setup.a_stop,
-                                    setup.n_steps)
+    co = step_coefficients(setup)
     disp, mom = co.D0 * s, co.G0 * s
     if s2 is not None:
         disp = disp + co.D20 * s2
@@ -198,8 +211,7 @@ def initial_state(s, setup, s2=None):
 def forward_from_displacement(s, setup, theta=None, s2=None):
     """N KDK steps from x_0 = q + D(a_0) s (+ D2(a_0) s2), p_0 = G(a_0) s
     (+ G2(a_0) s2) for given s, s2 [P, 3]."""
-    co = cosmo_mod.kdk_coefficients(setup.cosmo.omega_m, setup.a_start, setup.a_stop,
-                                    setup.n_steps)
+    co = step_coefficients(setup)
     q = lattice(setup.ptcl_grid, setup.box)
     disp, mom = initial_state(s, setup, s2)
     run = Run(setup=setup, theta=theta, s=s, s2=s2, mom0=mom.copy())
@@ -224,8 +236,7 @@ def reverse_reconstruct(disp_N, mom_N, setup, theta=None):
     reconstructed positions.  Returns the list of reconstructed displacements
     (index n = 0..N) and p_0.
     """
-    co = cosmo_mod.kdk_coefficients(setup.cosmo.omega_m, setup.a_start, setup.a_stop,
-                                    setup.n_steps)
+    co = step_coefficients(setup)
     q = lattice(setup.ptcl_grid, setup.box)
     disp, mom = disp_N.copy(), mom_N.copy()
     out = [None] * (setup.n_steps + 1)
@@ -257,6 +268,7 @@ class Gradients:
     pi0: np.ndarray
     D20: float = 0.0
     G20: float = 0.0
+    step_scales: np.ndarray = None   # [3, N] dL/d(scale) of kick_a, drift, kick_b
 
 
 def adjoint(run, noise, g_dens=None, g_disp=None, g_mom=None):
@@ -269,11 +281,12 @@ def adjoint(run, noise, g_dens=None, g_disp=None, g_mom=None):
       end     xi += J_F(x_0)^T [kick_a_0 pi]
     The scalar cotangents dL/dkick_a_n = Sum pi.F_n, dL/dkick_b_n = Sum pi.F_{n+1}
     and dL/ddrift_n = Sum xi.p_{n+1/2} are recorded on the way and combined
-    with dcoefficient/dOmega_m; the ICs add the D0, G0 and P(k) terms.
+    with dcoefficient/dOmega_m; the ICs add the D0, G0 and P(k) terms.  Times
+    the unscaled factors they are the gradients of the per-step scales.
     """
     st = run.setup
     N = st.n_steps
-    co = cosmo_mod.kdk_coefficients(st.cosmo.omega_m, st.a_start, st.a_stop, N)
+    co = step_coefficients(st)
     q = lattice(st.ptcl_grid, st.box)
     P = st.n_particles
     xN = q + run.disp[-1]
@@ -316,6 +329,11 @@ def adjoint(run, noise, g_dens=None, g_disp=None, g_mom=None):
     g_noise = zeldovich_transpose(s_bar, st.box, radial)
     g_sigma8 = float(np.sum(s_bar * s)) / st.cosmo.sigma8
     dco = cosmo_mod.kdk_coefficient_derivatives(st.cosmo.omega_m, st.a_start, st.a_stop, N)
+    base = cosmo_mod.kdk_coefficients(st.cosmo.omega_m, st.a_start, st.a_stop, N)
+    g_scales = np.stack([g_ka * base.kick_a, g_dr * base.drift, g_kb * base.kick_b])
+    if st.step_scales is not None:
+        sc = np.asarray(st.step_scales, dtype=np.float64).reshape(3, N)
+        dco.kick_a, dco.drift, dco.kick_b = dco.kick_a * sc[0], dco.drift * sc[1], dco.kick_b * sc[2]
     s_dom = zeldovich_displacement(noise, st.box,
                                    ic_radial_domega_m(st.ptcl_grid, st.box, st.cosmo))
     g_om = (np.dot(g_ka, dco.kick_a) + np.dot(g_kb, dco.kick_b) + np.dot(g_dr, dco.drift)
@@ -335,7 +353,7 @@ def adjoint(run, noise, g_dens=None, g_disp=None, g_mom=None):
         g_om += gD20 * dco.D20 + gG20 * dco.G20 + float(np.sum(s2_bar * s2_dom))
     return Gradients(noise=g_noise, omega_m=float(g_om), sigma8=g_sigma8, theta=g_theta,
                      kick_a=g_ka, kick_b=g_kb, drift=g_dr, D0=gD0, G0=gG0,
-                     xi0=xi, pi0=pi, D20=gD20, G20=gG20)
+                     xi0=xi, pi0=pi, D20=gD20, G20=gG20, step_scales=g_scales)
 
 
 # ------------------------------------------------------------- losses

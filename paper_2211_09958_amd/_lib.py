@@ -27,7 +27,8 @@ EXPORTS = ("pm_workspace_bytes", "pm_host_tables", "pm_init", "pm_set_cosmology"
            "pm_set_filter", "pm_forward", "pm_adjoint", "pm_loss_mse", "pm_loss_pk",
            "pm_loss_disp", "pm_power_spectrum",
            "pm_density", "pm_force", "pm_force_vjp", "pm_fft_r2c", "pm_fft_c2r",
-           "pm_lpt2_growth", "pm_initial_conditions",
+           "pm_lpt2_growth", "pm_initial_conditions", "pm_set_step_scales",
+           "pm_step_gradients",
            "pm_filter_table", "pm_adam", "pm_stats_get", "pm_stats_reset", "pm_destroy",
            "pm_last_error")
 
@@ -92,6 +93,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "pm_fft_c2r": (c_int, [P, P, P]),
         "pm_lpt2_growth": (c_int, [POINTER(Config), POINTER(Cosmology), P]),
         "pm_initial_conditions": (c_int, [P, P, P, P]),
+        "pm_set_step_scales": (c_int, [P, P]),
+        "pm_step_gradients": (c_int, [P, P]),
         "pm_filter_table": (c_int, [P, c_double, P]),
         "pm_adam": (c_int, [P, P, P, c_int32, P, P, c_int32, c_double, c_double, c_double, c_double,
                             c_int32]),

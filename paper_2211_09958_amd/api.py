@@ -149,6 +149,21 @@ class PMContext:
         self._check(self.lib.pm_forward(self.ctx, _ptr(noise), _ptr(disp), _ptr(mom), _ptr(dens)))
         return disp, mom, dens
 
+    def set_step_scales(self, scales):
+        """Per-step multipliers [3, n_steps] of kick_a, drift, kick_b (host array)."""
+        import numpy as np
+        sc = np.ascontiguousarray(np.asarray(scales, dtype=np.float64).reshape(-1))
+        if sc.size != 3 * self.cfg.n_steps:
+            raise ValueError(f"need {3 * self.cfg.n_steps} scales")
+        self._check(self.lib.pm_set_step_scales(self.ctx, sc.ctypes.data_as(c_void_p)))
+
+    def step_gradients(self):
+        """dL/d(step scales) [3, n_steps] of the last adjoint."""
+        import numpy as np
+        out = np.zeros(3 * self.cfg.n_steps)
+        self._check(self.lib.pm_step_gradients(self.ctx, out.ctypes.data_as(c_void_p)))
+        return out.reshape(3, self.cfg.n_steps)
+
     def initial_conditions(self, noise):
         """(x_0 - q, p_0) [P, 3] exactly as pm_forward starts (Zel'dovich or 2LPT)."""
         noise = self._in(noise, (self.np,) * 3)

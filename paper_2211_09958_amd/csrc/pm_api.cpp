@@ -187,7 +187,11 @@ struct pm_ctx {
     Twiddles twd;
     double *partials, *sums, *pkbins;
     unsigned* maxbits;
-    Schedule sched, dsched;
+    Schedule sched, dsched;         // KDK factors in use (scaled) and their d/dOmega_m
+    Schedule sched0;                // the unscaled growth-factor schedule
+    std::vector<double> step_scale; // [3N] multipliers of kick_a | drift | kick_b
+    std::vector<double> g_step;     // [3N] dL/d(step_scale) of the last adjoint
+    bool have_step_grads = false;
     bool have_forward = false;
     bool have_filter = false;
     std::string err;
@@ -268,12 +272,28 @@ double mesh_c(int n) { return 8.0 * n * (double)n * (n / 2 + 1); }
         if (_rc != PM_OK) return _rc; \
     } while (0)
 
+// Multiply the schedule's kick/drift factors (and their Omega_m derivatives)
+// by the per-step scales; sched0 keeps the unscaled factors.
+void apply_step_scales(pm_ctx* ctx) {
+    const int N = ctx->cfg.n_steps;
+    if (ctx->step_scale.empty()) ctx->step_scale.assign(3 * (size_t)N, 1.0);
+    ctx->sched0 = ctx->sched;
+    const double* f = ctx->step_scale.data();
+    for (Schedule* t : {&ctx->sched, &ctx->dsched})
+        for (int n = 0; n < N; ++n) {
+            t->kick_a[n] *= f[n];
+            t->drift[n] *= f[N + n];
+            t->kick_b[n] *= f[2 * N + n];
+        }
+}
+
 // Upload the cosmology-dependent tables (schedule on host; P(k) tables to the GPU).
 int upload_tables(pm_ctx* ctx) {
     const pm_config& c = ctx->cfg;
     Cosmo co = to_cosmo(&ctx->cosmo);
     ctx->sched = schedule(co.omega_m, c.a_start, c.a_stop, c.n_steps);
     ctx->dsched = schedule_domega(co.omega_m, c.a_start, c.a_stop, c.n_steps);
+    apply_step_scales(ctx);
     const int np = ctx->np, ng = ctx->ng;
     const long ntp = ctx->plan.ntab_p, ntf = ctx->plan.ntab_f;
     std::vector<double> pk = pk_table(co, c.box, (int)(ntp - 1));
@@ -756,6 +776,31 @@ int pm_set_cosmology(pm_ctx* ctx, const pm_cosmology* cosmo) {
     return upload_tables(ctx);
 }
 
+int pm_set_step_scales(pm_ctx* ctx, const double* scales) {
+    PM_TRY(ctx_check(ctx));
+    if (!scales) return ctx->fail(PM_EINVAL, "scales are null");
+    const int N = ctx->cfg.n_steps;
+    for (int i = 0; i < 3 * N; ++i)
+        if (!std::isfinite(scales[i])) return ctx->fail(PM_EINVAL, "step scales must be finite");
+    ctx->step_scale.assign(scales, scales + 3 * (size_t)N);
+    Cosmo co = to_cosmo(&ctx->cosmo);
+    const pm_config& c = ctx->cfg;
+    ctx->sched = schedule(co.omega_m, c.a_start, c.a_stop, N);
+    ctx->dsched = schedule_domega(co.omega_m, c.a_start, c.a_stop, N);
+    apply_step_scales(ctx);
+    ctx->have_forward = false;
+    ctx->have_step_grads = false;
+    return PM_OK;
+}
+
+int pm_step_gradients(pm_ctx* ctx, double* out) {
+    PM_TRY(ctx_check(ctx));
+    if (!out) return ctx->fail(PM_EINVAL, "out is null");
+    if (!ctx->have_step_grads) return ctx->fail(PM_ESTATE, "no pm_adjoint since the last pm_forward");
+    std::memcpy(out, ctx->g_step.data(), ctx->g_step.size() * sizeof(double));
+    return PM_OK;
+}
+
 int pm_set_filter(pm_ctx* ctx, const float* weights_dev) {
     PM_TRY(ctx_check(ctx));
     if (!ctx->cfg.filter) return ctx->fail(PM_ESTATE, "context was created with filter = 0");
@@ -770,6 +815,7 @@ int pm_forward(pm_ctx* ctx, const float* noise, float* disp_out, float* mom_out,
     PM_TRY(ctx_check(ctx));
     if (!noise || !disp_out || !mom_out) return ctx->fail(PM_EINVAL, "noise, disp and mom are required");
     if (ctx->cfg.filter && !ctx->have_filter) return ctx->fail(PM_ESTATE, "pm_set_filter not called");
+    ctx->have_step_grads = false;
     hipStream_t s = ctx->stream;
     const pm_config& c = ctx->cfg;
     const Schedule& sc = ctx->sched;
@@ -972,6 +1018,14 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
     const double g_s8 = (h[xSig] + 2.0 * h[xSig2]) / ctx->cosmo.sigma8;
     for (double v : h)
         if (!std::isfinite(v)) return ctx->fail(PM_ENUMERIC, "non-finite adjoint sum");
+    // dL/d(scale) = unscaled factor * dL/d(factor) per step
+    ctx->g_step.assign(3 * (size_t)N, 0.0);
+    for (int n = 0; n < N; ++n) {
+        ctx->g_step[n] = h[slotS + n] * ctx->sched0.kick_a[n];
+        ctx->g_step[N + n] = h[slotD + n] * ctx->sched0.drift[n];
+        ctx->g_step[2 * N + n] = h[slotS + n + 1] * ctx->sched0.kick_b[n];
+    }
+    ctx->have_step_grads = true;
     if (g_cosmo) {
         g_cosmo[0] = g_om;
         g_cosmo[1] = g_s8;

@@ -12,6 +12,11 @@ Every arithmetic step runs in libpmx through the C ABI: fine and coarse forward
 runs, the two losses and their cotangents (pm_loss_pk, pm_loss_disp), the
 reverse-time adjoint with the filter gradient, and Adam on the batch mean.
 
+The temporal half (``--train schedule`` or ``both``): per-step multipliers of
+the kick and drift factors (pm_set_step_scales), trained with Adam on the
+gradients the same adjoint returns (pm_step_gradients), alone or jointly with
+the filter.
+
     python -m paper_2211_09958_amd.train_filter --out weights.npy --report report.json
 
 Defaults: 128^3 particles, coarse 128^3 and fine 512^3 meshes, box 128 Mpc/h, 31
@@ -52,6 +57,10 @@ def parse(argv=None):
     p.add_argument("--n-bins", type=int, default=0, help="P(k) shells in the loss (0: Ng/2)")
     p.add_argument("--init-seed", type=int, default=0)
     p.add_argument("--init", default="", help="start from these weights (.npy) instead")
+    p.add_argument("--train", choices=("filter", "schedule", "both"), default="filter",
+                   help="what to learn: the force filter, the per-step KDK scales, or both")
+    p.add_argument("--lr-schedule", type=float, default=1e-3, help="Adam rate of the step scales")
+    p.add_argument("--out-schedule", default="", help="write the step scales (.npy, [3, steps])")
     p.add_argument("--out", default="", help="write the trained weights (.npy, float32)")
     p.add_argument("--report", default="", help="write losses and held-out errors (.json)")
     p.add_argument("--log-every", type=int, default=1)
@@ -85,30 +94,49 @@ class Trainer:
         self.m = torch.zeros_like(self.theta)
         self.v = torch.zeros_like(self.theta)
         self.grads = torch.empty((a.batch, N_FILTER_PARAMS), dtype=torch.float32, device=self.dev)
+        self.train_filter = a.train in ("filter", "both")
+        self.train_schedule = a.train in ("schedule", "both")
+        ns = 3 * a.steps
+        self.scales = torch.ones(ns, dtype=torch.float32, device=self.dev)
+        self.sm = torch.zeros_like(self.scales)
+        self.sv = torch.zeros_like(self.scales)
+        self.sgrads = torch.empty((a.batch, ns), dtype=torch.float32, device=self.dev)
         self.t = 0
 
     def step(self, batch):
-        """One Adam step on the mean filter gradient of the runs in `batch`."""
+        """One Adam step on the mean gradient (filter weights and/or step scales)
+        of the runs in `batch`."""
         c = self.coarse
         c.set_filter(self.theta)
+        c.set_step_scales(self.scales.cpu().numpy())
         lp = ld = 0.0
         for i, s in enumerate(batch):
             disp, _, dens = c.forward(self.noise[s])
             Lp, g_dens = c.loss_pk(dens, self.pk_f[s], self.n_bins)
             Ld, g_disp = c.loss_disp(disp, self.disp_f[s], weight=self.a.w_disp)
-            c.adjoint(g_dens=g_dens, g_disp=g_disp, g_filter_out=self.grads[i])
+            c.adjoint(g_dens=g_dens, g_disp=g_disp,
+                      g_filter_out=self.grads[i] if self.train_filter else None)
+            if self.train_schedule:
+                self.sgrads[i].copy_(torch.as_tensor(c.step_gradients().reshape(-1),
+                                                     dtype=torch.float32))
             lp += Lp
             ld += Ld
         self.t += 1
-        c.adam(self.theta, self.grads[:len(batch)], self.m, self.v, self.t, lr=self.a.lr)
+        if self.train_filter:
+            c.adam(self.theta, self.grads[:len(batch)], self.m, self.v, self.t, lr=self.a.lr)
+        if self.train_schedule:
+            c.adam(self.scales, self.sgrads[:len(batch)], self.sm, self.sv, self.t,
+                   lr=self.a.lr_schedule)
         return lp / len(batch), ld / len(batch)
 
-    def evaluate(self, theta, seeds):
+    def evaluate(self, theta, seeds, scales=None):
         """P(k) error against the fine run on the common coarse mesh, per held-out
         seed: max over shells with k <= k_Nyq/2 of |P/P_fine - 1|; and the RMS
         position error in coarse cells."""
         c = self.coarse
         c.set_filter(theta)
+        c.set_step_scales(np.ones(3 * self.a.steps) if scales is None
+                          else scales.cpu().numpy())
         half = self.a.ptcl // 4   # shell b ~ |n|; k_Nyq/2 is |n| = Ng/4
         errs, rms, ratios = [], [], []
         for s in seeds:
@@ -152,7 +180,7 @@ def main(argv=None):
     report = {"config": vars(a), "train_seconds": train_s, "adam_steps": tr.t, "history": history}
     if held:
         report["heldout_plain"] = tr.evaluate(plain, held)
-        report["heldout_learned"] = tr.evaluate(tr.theta, held)
+        report["heldout_learned"] = tr.evaluate(tr.theta, held, tr.scales)
         print(f"held-out max |P/P_fine - 1| (k <= k_Nyq/2): plain "
               f"{report['heldout_plain']['pk_maxerr_half_nyq_mean']:.4f}, learned "
               f"{report['heldout_learned']['pk_maxerr_half_nyq_mean']:.4f}; position rms cells: "
@@ -160,6 +188,10 @@ def main(argv=None):
               f"{report['heldout_learned']['pos_rms_cells_mean']:.4f}", flush=True)
     if a.out:
         np.save(a.out, tr.theta.cpu().numpy().astype(np.float32))
+    if a.out_schedule:
+        np.save(a.out_schedule, tr.scales.cpu().numpy().reshape(3, a.steps).astype(np.float64))
+    if tr.train_schedule:
+        report["step_scales"] = tr.scales.cpu().numpy().reshape(3, a.steps).tolist()
     if a.report:
         with open(a.report, "w") as f:
             json.dump(report, f, indent=1)
