@@ -27,6 +27,11 @@ PEAK_HBM_GBS = 8000.0
 CPU_STEPS = 10          # oracle sample: about 10-20 s on a 16-core host
 # trained against the 2x-finer mesh, the resolution of the plain run it is compared with
 WEIGHTS = os.path.join(ROOT, "paper_2211_09958_amd", "weights", "filter_128p_128m_to_256m.npy")
+# per-step KDK scales trained at 63 steps (alone, and jointly with a filter)
+SCHEDULE = os.path.join(ROOT, "paper_2211_09958_amd", "weights",
+                        "schedule_128p_128m_63s_to_256m.npy")
+JOINT = (os.path.join(ROOT, "paper_2211_09958_amd", "weights", "joint_filter_128p_128m_63s_to_256m.npy"),
+         os.path.join(ROOT, "paper_2211_09958_amd", "weights", "joint_schedule_128p_128m_63s_to_256m.npy"))
 FAMILY_KERNELS = {
     "fft_strided": ["k_fft_strided", "k_fft_y_split"], "fft_x": ["k_fft_x_r2c", "k_fft_x_c2r"],
     "grad_z": ["k_grad_z"], "grad_adj_z": ["k_grad_adj_z"],
@@ -325,6 +330,21 @@ def learned_vs_plain(args, co, noise, disp_plain, plain_value):
     err = lambda pk: float(np.max(np.abs(pk[:half] / pk_ref[:half] - 1.0)))
     worst = lambda pk: int(np.argmax(np.abs(pk[:half] / pk_ref[:half] - 1.0))) + 1
     e_l, e_p = err(pk_learned), err(pk_plain)
+    # the temporal half: learned per-step scales, alone and with their jointly
+    # trained filter (accuracy only: the scales leave the cost of a run unchanged)
+    temporal = {}
+    if os.path.exists(SCHEDULE):
+        plain.set_step_scales(np.load(SCHEDULE))
+        pk = plain.power_spectrum(plain.forward(noise)[2], w.mesh // 2)[1]
+        temporal["schedule_only_512"] = {"pk_maxerr_to_half_nyq": err(pk), "worst_shell": worst(pk),
+                                         "scales": os.path.relpath(SCHEDULE, ROOT)}
+    if all(os.path.exists(f) for f in JOINT):
+        lp.set_filter(torch.as_tensor(np.load(JOINT[0]).astype(np.float32), device="cuda:0"))
+        lp.set_step_scales(np.load(JOINT[1]))
+        pk = lp.power_spectrum(lp.forward(noise)[2], w.mesh // 2)[1]
+        temporal["filter_and_schedule_512"] = {"pk_maxerr_to_half_nyq": err(pk),
+                                               "worst_shell": worst(pk),
+                                               "weights": [os.path.relpath(f, ROOT) for f in JOINT]}
     return {"workload": f"{w.name} learned f(|k|,a)", "value": value, "unit": "particle-steps/s",
             "ms_per_step": dt / args.steps * 1e3, "speedup_vs_plain_1024": value / plain_value,
             "pk_maxerr_to_half_nyq": {"learned_512": e_l, "plain_512": e_p},
@@ -333,7 +353,8 @@ def learned_vs_plain(args, co, noise, disp_plain, plain_value):
                                              (pk_learned[:16] / pk_ref[:16])],
             "reference": "plain 512^3 particles on the 1024^3 mesh, same seed; all P(k) on the "
                          "512^3 mesh",
-            "within_2pct": e_l <= 0.02, "weights": os.path.relpath(args.weights, ROOT)}
+            "within_2pct": e_l <= 0.02, "weights": os.path.relpath(args.weights, ROOT),
+            "temporal": temporal}
 
 
 if __name__ == "__main__":

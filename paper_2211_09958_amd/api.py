@@ -297,25 +297,31 @@ class PMContext:
 
 
 class Simulate(torch.autograd.Function):
-    """(noise, omega_m, sigma8, filter weights) -> (disp, mom, dens).
+    """(noise, omega_m, sigma8, filter weights, step scales) -> (disp, mom, dens).
 
     forward calls pm_forward; backward calls pm_adjoint (the reverse-time
-    adjoint), returning dL/dnoise, dL/dOmega_m, dL/dsigma_8 and dL/dweights.
-    omega_m and sigma8 are 0-d tensors (their values update the context's
-    cosmology when they change); weights may be None for the plain force.
+    adjoint), returning dL/dnoise, dL/dOmega_m, dL/dsigma_8, dL/dweights and
+    dL/d(step scales).  omega_m and sigma8 are 0-d tensors (their values update
+    the context's cosmology when they change); weights may be None for the plain
+    force; step_scales ([3, n_steps] multipliers of kick_a, drift, kick_b) may be
+    None for plain KDK.
     """
 
     @staticmethod
-    def forward(fctx, pm: PMContext, noise, omega_m, sigma8, weights):
+    def forward(fctx, pm: PMContext, noise, omega_m, sigma8, weights, step_scales):
         from dataclasses import replace
         om, s8 = float(omega_m), float(sigma8)
         if om != pm.cosmo.omega_m or s8 != pm.cosmo.sigma8:
             pm.set_cosmology(replace(pm.cosmo, omega_m=om, sigma8=s8))
         if weights is not None:
             pm.set_filter(weights.detach().contiguous())
+        if step_scales is not None:
+            pm.set_step_scales(step_scales.detach().double().cpu().numpy())
         disp, mom, dens = pm.forward(noise.detach().contiguous())
         fctx.pm = pm
         fctx.has_w = weights is not None
+        fctx.scales = None if step_scales is None else (step_scales.shape, step_scales.dtype,
+                                                        step_scales.device)
         fctx.dev = noise.device
         return disp, mom, dens
 
@@ -325,8 +331,13 @@ class Simulate(torch.autograd.Function):
         c = lambda t: None if t is None else t.contiguous()
         g_noise, (g_om, g_s8), g_w = pm.adjoint(c(g_dens), c(g_disp), c(g_mom), want_filter=fctx.has_w)
         dev = fctx.dev
-        return (None, g_noise, torch.tensor(g_om, device=dev), torch.tensor(g_s8, device=dev), g_w)
+        g_sc = None
+        if fctx.scales is not None:
+            shape, dtype, sdev = fctx.scales
+            g_sc = torch.as_tensor(pm.step_gradients(), dtype=dtype, device=sdev).reshape(shape)
+        return (None, g_noise, torch.tensor(g_om, device=dev), torch.tensor(g_s8, device=dev), g_w,
+                g_sc)
 
 
-def simulate(pm: PMContext, noise, omega_m, sigma8, weights=None):
-    return Simulate.apply(pm, noise, omega_m, sigma8, weights)
+def simulate(pm: PMContext, noise, omega_m, sigma8, weights=None, step_scales=None):
+    return Simulate.apply(pm, noise, omega_m, sigma8, weights, step_scales)

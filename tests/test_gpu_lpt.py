@@ -37,7 +37,7 @@ def oracle_ics(w, noise):
     return s1, s2, opm.initial_state(s1, st, s2)
 
 
-@pytest.mark.parametrize("np_,ng,box", [(8, 16, 32.0), (16, 16, 32.0), (32, 64, 64.0),
+@pytest.mark.parametrize("np_,ng,box", [(8, 8, 16.0), (8, 16, 32.0), (16, 16, 32.0), (32, 64, 64.0),
                                         (64, 128, 128.0)])
 def test_lpt2_initial_state_matches_oracle(np_, ng, box):
     """The state is stored in fixed point: positions in units of box / 2^32 and

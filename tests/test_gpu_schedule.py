@@ -95,3 +95,59 @@ def test_schedule_training_reduces_loss():
     print(f"schedule training loss {first:.4e} -> {last:.4e}")
     assert last < 0.9 * first
     assert not torch.equal(tr.scales, torch.ones_like(tr.scales))
+
+
+def test_autograd_function_with_step_scales():
+    w = TINY
+    pm = fresh(w)
+    scales_np = 1.0 + 0.05 * normal((3, w.n_steps), 72)
+    noise = dev(white_noise(8, 2)).requires_grad_(True)
+    om = torch.tensor(CO.omega_m, dtype=torch.float64, requires_grad=True)
+    s8 = torch.tensor(CO.sigma8, dtype=torch.float64, requires_grad=True)
+    scales = torch.tensor(scales_np, dtype=torch.float64, requires_grad=True)
+    disp, mom, dens = api.simulate(pm, noise, om, s8, None, scales)
+    (dens.double() ** 2).mean().backward()
+    st = replace(setup_for(w), step_scales=scales_np)
+    run = opm.forward(white_noise(8, 2), st)
+    ref = opm.adjoint(run, white_noise(8, 2), g_dens=2 * run.dens / run.dens.size)
+    assert scales.grad.shape == (3, w.n_steps)
+    assert rel_l2(scales.grad.numpy(), ref.step_scales) < 1e-3
+    assert rel_l2(host(noise.grad), ref.noise) < 1e-3
+
+
+def test_all_options_together_match_oracle():
+    """2LPT ICs, learned filter, step scales and checkpoints in one run: every
+    gradient against the oracle, and the checkpointed adjoint against the pure one."""
+    from oracle import mlp as omlp
+    from synthetic import mlp_init
+    w = SMALL
+    theta = 0.3 * mlp_init(1, zero_last=False)
+    scales = 1.0 + 0.05 * normal((3, w.n_steps), 73)
+    st = replace(setup_for(w, 2), step_scales=scales)
+    noise = white_noise(w.ptcl_grid, 3)
+    target = opm.forward(white_noise(w.ptcl_grid, 4), st).dens
+    run = opm.forward(noise, st, theta)
+    _, gd_ref = opm.mse_loss(run.dens, target)
+    ref = opm.adjoint(run, noise, g_dens=gd_ref)
+    out = []
+    for ck in (0, 3):
+        cfg = api.make_config(w.ptcl_grid, w.mesh, w.box, w.n_steps, checkpoint_every=ck,
+                              filter=True, lpt_order=2)
+        pm = api.PMContext(cfg, CO)
+        pm.set_filter(dev(theta))
+        pm.set_step_scales(scales)
+        disp, _, dens = pm.forward(dev(noise))
+        _, gd = pm.loss_mse(dens, dev(target))
+        g_noise, (g_om, g_s8), g_w = pm.adjoint(gd, want_filter=True)
+        out.append((host(g_noise), g_om, g_s8, host(g_w), pm.step_gradients(), pm.stats()))
+    for g_noise, g_om, g_s8, g_w, g_steps, stats in out:
+        d = periodic_cells(host(disp), run.disp[-1], w.box, w.mesh)
+        assert np.sqrt(np.mean(d * d)) < 1e-3
+        assert rel_l2(g_noise, ref.noise) < 1e-3
+        assert rel_l2(g_w, ref.theta) < 1e-3
+        assert rel_l2(g_steps, ref.step_scales) < 1e-3
+        assert abs(g_s8 / ref.sigma8 - 1) < 1e-3
+        assert stats["ic_max_cells"] == 0.0
+    assert out[1][5]["n_checkpoints"] == 3 and max(out[1][5]["ckpt_max_cells"]) == 0.0
+    assert rel_l2(out[1][0], out[0][0]) < 1e-4
+    assert rel_l2(out[1][4], out[0][4]) < 1e-4
