@@ -110,3 +110,20 @@ def test_lpt_order_sets_the_flag():
     assert api.make_config(32, 64, 64.0, 10).flags == 0
     with pytest.raises(ValueError):
         api.make_config(32, 64, 64.0, 10, lpt_order=3)
+
+
+def test_new_calls_validate_on_the_host():
+    lib = _lib.load()
+    cfg = api.config_from_workload(SMALL)
+    cs = api._cosmo_struct(CO)
+    out = np.zeros(4)
+    assert lib.pm_lpt2_growth(ctypes.byref(cfg), ctypes.byref(cs), None) == _lib.PM_EINVAL
+    assert lib.pm_lpt2_growth(None, ctypes.byref(cs), out.ctypes.data_as(ctypes.c_void_p)) == _lib.PM_EINVAL
+    bad = api._cosmo_struct(CO)
+    bad.omega_m = 2.0
+    assert lib.pm_lpt2_growth(ctypes.byref(cfg), ctypes.byref(bad),
+                              out.ctypes.data_as(ctypes.c_void_p)) == _lib.PM_EINVAL
+    scales = np.ones(3 * SMALL.n_steps)
+    assert lib.pm_set_step_scales(None, scales.ctypes.data_as(ctypes.c_void_p)) == _lib.PM_EINVAL
+    assert lib.pm_step_gradients(None, scales.ctypes.data_as(ctypes.c_void_p)) == _lib.PM_EINVAL
+    assert lib.pm_initial_conditions(None, None, None, None) == _lib.PM_EINVAL
