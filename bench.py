@@ -51,6 +51,8 @@ def parse():
     p.add_argument("--checkpoint-every", type=int, default=16)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-pure-variant", action="store_true")
+    p.add_argument("--no-medium", action="store_true",
+                   help="skip the 256^3-particle / 512^3-mesh run reported beside the headline")
     p.add_argument("--no-learned", action="store_true",
                    help="skip the learned-filter 512^3-mesh vs plain 1024^3-mesh comparison")
     p.add_argument("--weights", default=WEIGHTS, help="trained filter weights (.npy)")
@@ -228,6 +230,10 @@ def main():
         out["pure_reverse"] = {"value": P * w.n_steps / dtp, "ms_per_step": dtp * 1e3,
                                "ic_rms_cells": sp["ic_rms_cells"],
                                "ic_max_cells": sp["ic_max_cells"]}
+    if not args.no_medium and w.name == "pm-512p-1024m-63s":
+        pm = pure = None
+        torch.cuda.empty_cache()
+        out["medium"] = medium_leg(args, co)
     if not args.no_lpt2:
         pm = pure = None
         torch.cuda.empty_cache()
@@ -239,6 +245,39 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
+
+
+def medium_leg(args, co):
+    """The same forward + MSE loss + adjoint run at 256^3 particles / 512^3 mesh /
+    box 256 / 63 steps (pure reverse time), seeds 0 (run) and 1 (target):
+    1 warm-up, then `steps` timed runs."""
+    import torch
+
+    from paper_2211_09958_amd import api
+    from synthetic import MEDIUM, white_noise
+    w = MEDIUM
+    pm = api.PMContext(api.config_from_workload(w), co, device="cuda:0")
+    dev = lambda seed: torch.as_tensor(white_noise(w.ptcl_grid, seed), dtype=torch.float32,
+                                       device="cuda:0")
+    noise = dev(0)
+    target = pm.forward(dev(1))[2].clone()
+
+    def run():
+        disp, mom, dens = pm.forward(noise)
+        _, g = pm.loss_mse(dens, target)
+        return pm.adjoint(g_dens=g)[1]
+
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g_cosmo = run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    st = pm.stats()
+    return {"workload": w.name, "value": w.ptcl_grid ** 3 * w.n_steps / dt,
+            "unit": "particle-steps/s", "ms_per_run": dt * 1e3, "ic_max_cells": st["ic_max_cells"],
+            "grad_cosmo": list(g_cosmo)}
 
 
 def lpt2_leg(args, w, co, noise, target, plain_fams, make):
