@@ -258,3 +258,72 @@ def test_power_spectrum_vjp_matches_finite_difference():
     fd = (F(d + h * u) - F(d - h * u)) / (2 * h)
     an = float(np.sum(M.power_spectrum_vjp(d, box, nbins, g_pk) * u))
     assert abs(fd - an) < 1e-9 * abs(an)
+
+
+def _ewald_force(d, mass, box, alpha=None, nreal=2, nfour=8):
+    """Periodic force of a point mass with a neutralising background (lap(phi) =
+    mass (sum of deltas) - mass / box^3, F = -grad(phi)) at separations d [m, 3], by
+    Ewald summation (Hernquist, Bouchet & Suto 1991): a real-space erfc sum over
+    images plus a reciprocal-space sum."""
+    from scipy.special import erfc
+    alpha = 2.0 / box if alpha is None else alpha
+    out = np.zeros_like(d)
+    rng = range(-nreal, nreal + 1)
+    for n0 in rng:
+        for n1 in rng:
+            for n2 in rng:
+                s = d - box * np.array([n0, n1, n2])
+                r = np.linalg.norm(s, axis=1, keepdims=True)
+                g = erfc(alpha * r) + 2 * alpha * r / np.sqrt(np.pi) * np.exp(-(alpha * r) ** 2)
+                out -= mass / (4 * np.pi) * s / r ** 3 * g
+    h = np.arange(-nfour, nfour + 1)
+    hv = np.stack(np.meshgrid(h, h, h, indexing="ij"), axis=-1).reshape(-1, 3)
+    hv = hv[np.any(hv != 0, axis=1)]
+    k = 2 * np.pi / box * hv
+    k2 = np.sum(k * k, axis=1)
+    coef = np.exp(-k2 / (4 * alpha ** 2)) / k2
+    out -= mass / box ** 3 * (np.sin(d @ k.T) * coef) @ k
+    return out
+
+
+def test_ewald_reference_is_converged_and_odd():
+    box = 10.0
+    d = normal((8, 3), 14) * 2.0
+    a = _ewald_force(d, 1.0, box)
+    b = _ewald_force(d, 1.0, box, alpha=3.0 / box, nreal=3, nfour=12)
+    np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(_ewald_force(-d, 1.0, box), -a, rtol=1e-12)
+    # the force vanishes at the centre of the cell between images, by symmetry
+    assert np.max(np.abs(_ewald_force(np.array([[box / 2] * 3]), 1.0, box))) < 1e-12
+    # and tends to the bare inverse square close to the mass
+    near = np.array([[0.01, 0.0, 0.0]])
+    assert abs(-_ewald_force(near, 1.0, box)[0, 0] * 4 * np.pi * 0.01 ** 2 - 1) < 1e-5
+
+
+def test_two_particle_force_against_ewald():
+    """The probe's PM force from one mass against the Ewald-summed periodic force
+    for 4 cells <= r <= L/4: orientation-averaged radial component within 1%, mean
+    vector error within 3% at 4 cells and 0.5% from 8 cells on.  Directions within
+    15 degrees of a mesh axis are left out: truncating the exact spectral kernel to
+    the cube of mesh wave numbers rings (Gibbs) along the axis lines through the
+    mass, where the mesh force alternates from node to node (shown below)."""
+    mesh, box = 128, 128.0
+    src = np.array([[40.3, 61.7, 50.2]])
+    delta = M.density(src, mesh, box, 1)
+    F, _ = M.force_meshes(delta, box)
+    Mass = box ** 3
+    dirs = normal((400, 3), 15)
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    dirs = dirs[np.max(np.abs(dirs), axis=1) < np.cos(np.radians(15.0))][:128]
+    for r, tol_vec in ((4.0, 0.03), (6.0, 0.015), (8.0, 0.005), (16.0, 0.005), (32.0, 0.005)):
+        x = src + r * dirs
+        f = np.stack([M.gather(F[j], x, box) for j in range(3)], axis=1)
+        ref = _ewald_force(r * dirs, Mass, box)
+        rr = np.sum(f * dirs, axis=1) / np.sum(ref * dirs, axis=1)
+        vec = np.linalg.norm(f - ref, axis=1).mean() / np.linalg.norm(ref, axis=1).mean()
+        print(f"r = {r}: radial ratio {rr.mean():.4f} (anisotropy {rr.std():.4f}), vector {vec:.4f}")
+        assert abs(rr.mean() - 1) < 0.01, (r, rr.mean())
+        assert vec < tol_vec, (r, vec)
+    # on the axis line through the mass the node values alternate in sign
+    line = F[0][42:60, 61, 49]
+    assert np.any(line > 0) and np.any(line < 0)
