@@ -138,21 +138,24 @@ k_bin_count(const uint32_t* __restrict__ xq, Lattice L, int tile, int nt, long P
                        (ii[2] % tile == tile - 1);
         key = tix * 8 + cls;
     }
-    // one atomic per distinct key in the wave; rank = slot inside the bin
+    // one atomic per distinct key in the wave, all issued together: group the
+    // lanes by key first (no memory traffic), then every group's first lane adds
+    // the group size, and rank = that slot + the lane's place in its group
     const int lane = __lane_id();
     unsigned long long pending = __ballot(valid);
-    uint32_t rank = 0;
+    unsigned long long mine = 0ull;   // lanes sharing this lane's key
     while (pending) {
         const int leader = __ffsll((long long)pending) - 1;
         const uint32_t lk = (uint32_t)__shfl((int)key, leader);
         const unsigned long long same = __ballot(key == lk) & pending;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&counts[lk], (uint32_t)__popcll(same));
-        base = (uint32_t)__shfl((int)base, leader);
-        if ((same >> lane) & 1ull)
-            rank = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+        if ((same >> lane) & 1ull) mine = same;
         pending &= ~same;
     }
+    const int first = valid ? __ffsll((long long)mine) - 1 : lane;
+    uint32_t base = 0;
+    if (valid && lane == first) base = atomicAdd(&counts[key], (uint32_t)__popcll(mine));
+    base = (uint32_t)__shfl((int)base, first);
+    const uint32_t rank = base + (uint32_t)__popcll(mine & ((1ull << lane) - 1ull));
     if (valid) {
         keys[i] = key;
         ranks[i] = rank;
