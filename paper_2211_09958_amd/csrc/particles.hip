@@ -234,25 +234,36 @@ k_scan_add(uint32_t* __restrict__ out, long n, const uint32_t* __restrict__ bsum
         if (base + k < n) out[base + k] += add;
 }
 
-// Move every record of particle i to its sorted slot offsets[key] + rank.
+// Move every record of particle i to its sorted slot offsets[key] + rank.  All
+// words are loaded before any is stored: interleaved, each load would wait for
+// the store before it (the record arrays are not known to be disjoint), one
+// memory round trip per word.
 __global__ void __launch_bounds__(kBlock)
 k_permute(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ ranks,
           const uint32_t* __restrict__ offsets, long P, Records rec) {
     const long i = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= P) return;
-    const long slot = offsets[keys[i]] + ranks[i];
+    const uint32_t key = keys[i], rank = ranks[i];
+    uint32_t buf[6][3];
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
-        if (a >= rec.n) break;
-        const int w = rec.words[a];
-        const uint32_t* src = rec.src[a] + i * w;
-        uint32_t* dst = rec.dst[a] + slot * w;
-        if (w == 3) {
-            dst[0] = src[0];
-            dst[1] = src[1];
-            dst[2] = src[2];
-        } else {
-            for (int k = 0; k < w; ++k) dst[k] = src[k];
+        if (a < rec.n) {
+            const int w = rec.words[a];
+            const uint32_t* src = rec.src[a] + i * w;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (k < w) buf[a][k] = src[k];
+        }
+    }
+    const long slot = offsets[key] + rank;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+        if (a < rec.n) {
+            const int w = rec.words[a];
+            uint32_t* dst = rec.dst[a] + slot * w;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (k < w) dst[k] = buf[a][k];
         }
     }
 }
