@@ -355,15 +355,27 @@ k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, 
     for (int comp = 0; comp < NC; ++comp) {
         for (int c = threadIdx.x; c < T3; c += scatter_threads()) acc[c] = 0ull;
         __syncthreads();
-        // one flat index space over the 20 ranges, so every lane has work
-        for (uint32_t k = threadIdx.x; k < total; k += scatter_threads()) {
+        // one flat index space over the 20 ranges, so every lane has work; the
+        // next particle's record is loaded before this one's atomics are issued
+        uint32_t nx[3] = {0u, 0u, 0u};
+        float nv = 0.f;
+        auto fetch = [&](uint32_t kk) {
             int r = 0;
-            while (pre[r + 1] <= k) ++r;
-            const long p = rs[r] + (k - pre[r]);   // particles are stored in bin order
+            while (pre[r + 1] <= kk) ++r;
+            const long p = rs[r] + (kk - pre[r]);   // particles are stored in bin order
+#pragma unroll
+            for (int a = 0; a < 3; ++a) nx[a] = xq[3 * p + a];
+            if (VEC) nv = vals[3 * p + comp];
+        };
+        if (threadIdx.x < total) fetch(threadIdx.x);
+        for (uint32_t k = threadIdx.x; k < total; k += scatter_threads()) {
+            const uint32_t cur[3] = {nx[0], nx[1], nx[2]};
+            const float cv = nv;
+            if (k + scatter_threads() < total) fetch(k + scatter_threads());
             int ii[3];
             float t[3];
-            locate(xq + 3 * p, L, ii, t);
-            const float val = VEC ? amp * vals[3 * p + comp] : amp;
+            locate(cur, L, ii, t);
+            const float val = VEC ? amp * cv : amp;
 #pragma unroll
             for (int c0 = 0; c0 < 2; ++c0) {
                 int l0 = ((ii[0] + c0) & mask) - lo[0];
