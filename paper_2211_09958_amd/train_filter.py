@@ -64,7 +64,32 @@ def parse(argv=None):
     p.add_argument("--out", default="", help="write the trained weights (.npy, float32)")
     p.add_argument("--report", default="", help="write losses and held-out errors (.json)")
     p.add_argument("--log-every", type=int, default=1)
+    p.add_argument("--state", default="",
+                   help="training state (.npz: weights, step scales, Adam moments, step count, "
+                        "epoch, shuffling RNG) written after every epoch and resumed from when "
+                        "it exists")
     return p.parse_args(argv)
+
+
+def save_state(path, tr, epoch, rng, history):
+    """Weights, step scales, their Adam moments and step count, the next epoch, the
+    shuffling RNG state and the loss history, written atomically."""
+    cpu = lambda t: t.detach().cpu().numpy()
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, theta=cpu(tr.theta), m=cpu(tr.m), v=cpu(tr.v), scales=cpu(tr.scales),
+             sm=cpu(tr.sm), sv=cpu(tr.sv), t=tr.t, epoch=epoch,
+             rng=json.dumps(rng.bit_generator.state), history=json.dumps(history))
+    os.replace(tmp, path)
+
+
+def load_state(path, tr, rng):
+    """Restore what save_state wrote; returns (next epoch, history)."""
+    with np.load(path) as z:
+        for name in ("theta", "m", "v", "scales", "sm", "sv"):
+            getattr(tr, name).copy_(torch.as_tensor(z[name]))
+        tr.t = int(z["t"])
+        rng.bit_generator.state = json.loads(str(z["rng"]))
+        return int(z["epoch"]), json.loads(str(z["history"]))
 
 
 class Trainer:
@@ -164,8 +189,12 @@ def main(argv=None):
                             device=tr.dev)
     history = []
     rng = np.random.Generator(np.random.PCG64(12345))
+    start = 0
+    if a.state and os.path.exists(a.state):
+        start, history = load_state(a.state, tr, rng)
+        print(f"resumed from {a.state} at epoch {start} (Adam step {tr.t})", flush=True)
     t1 = time.perf_counter()
-    for ep in range(a.epochs):
+    for ep in range(start, a.epochs):
         order = rng.permutation(train)
         lps, lds = [], []
         for b0 in range(0, len(order), a.batch):
@@ -173,6 +202,8 @@ def main(argv=None):
             lps.append(lp)
             lds.append(ld)
         history.append({"epoch": ep, "loss_pk": float(np.mean(lps)), "loss_disp": float(np.mean(lds))})
+        if a.state:
+            save_state(a.state, tr, ep + 1, rng, history)
         if ep % a.log_every == 0 or ep == a.epochs - 1:
             print(f"epoch {ep:4d}  loss_pk {np.mean(lps):.4e}  loss_disp {np.mean(lds):.4e}  "
                   f"{time.perf_counter() - t1:.1f} s", flush=True)

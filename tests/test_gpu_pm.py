@@ -7,7 +7,7 @@ from gpu_util import CO, context, ctx_for, dev, host, periodic_cells, rel_l2, se
 from oracle import mesh as M
 from oracle import mlp as omlp
 from oracle import pm as opm
-from paper_2211_09958_amd import api
+from paper_2211_09958_amd import _lib, api
 from synthetic import SMALL, Workload, mlp_init, normal, white_noise
 
 pytestmark = pytest.mark.gpu
@@ -285,3 +285,41 @@ def test_field_level_reconstruction_recovers_the_noise():
     r = np.array(rep["noise_cross_correlation"])
     print(np.round(r, 4))
     assert r[: 3 * len(r) // 4].min() > 0.95, r
+
+
+# ------------------------------------------------------- failure handling, resume
+
+def test_nonfinite_cotangent_reports_enumeric_and_context_recovers():
+    """A NaN cotangent makes the adjoint's FP64 sums non-finite: PM_ENUMERIC, and
+    the context stays usable (positions never depend on cotangents)."""
+    w = TINY
+    pm = api.PMContext(api.config_from_workload(w), CO)
+    noise = dev(white_noise(8, 2))
+    gd = dev(normal((512, 3), 3))
+    pm.forward(noise)
+    ref = pm.adjoint(g_disp=gd)[0].clone()
+    pm.forward(noise)
+    bad = torch.full((512, 3), float("nan"), device="cuda")
+    with pytest.raises(api.PMError) as e:
+        pm.adjoint(g_mom=bad)
+    assert e.value.code == _lib.PM_ENUMERIC
+    pm.forward(noise)
+    assert torch.equal(pm.adjoint(g_disp=gd)[0], ref)
+    assert pm.stats()["ic_max_cells"] == 0.0
+
+
+def test_filter_training_resumes_from_its_state(tmp_path):
+    """Two epochs in one go against one epoch, stop, resume for the second: the
+    same weights (up to the order of the FP64 filter-gradient atomics)."""
+    from paper_2211_09958_amd import train_filter as tf
+    base = ["--ptcl", "16", "--fine-factor", "2", "--box", "32", "--steps", "4",
+            "--train-seeds", "4", "--heldout", "0", "--batch", "2", "--n-bins", "8",
+            "--lr", "1e-2", "--log-every", "100"]
+    tf.main(base + ["--epochs", "2", "--out", str(tmp_path / "a.npy")])
+    st = str(tmp_path / "state.npz")
+    tf.main(base + ["--epochs", "1", "--state", st])
+    r = tf.main(base + ["--epochs", "2", "--state", st, "--out", str(tmp_path / "b.npy")])
+    a, b = np.load(tmp_path / "a.npy"), np.load(tmp_path / "b.npy")
+    assert r["adam_steps"] == 4 and len(r["history"]) == 2
+    assert not np.array_equal(a, mlp_init(0, zero_last=True))
+    assert np.max(np.abs(a - b)) <= 1e-5 * np.max(np.abs(a))
