@@ -127,3 +127,25 @@ def test_new_calls_validate_on_the_host():
     assert lib.pm_set_step_scales(None, scales.ctypes.data_as(ctypes.c_void_p)) == _lib.PM_EINVAL
     assert lib.pm_step_gradients(None, scales.ctypes.data_as(ctypes.c_void_p)) == _lib.PM_EINVAL
     assert lib.pm_initial_conditions(None, None, None, None) == _lib.PM_EINVAL
+
+
+def test_einstein_de_sitter_host_tables():
+    """Omega_m = 1 (no Lambda): D = a, G = a^3 E dD/da = a^(3/2), D2 = -(3/7) a^2,
+    G2 = -(6/7) a^(5/2), and kick/drift factors in closed form."""
+    from dataclasses import replace
+    co = replace(CO, omega_m=1.0)
+    cfg = api.make_config(32, 64, 64.0, 8, a_start=0.1, a_stop=0.9)
+    t = api.host_tables(cfg, co)
+    a = 0.1 + 0.1 * np.arange(9)
+    np.testing.assert_allclose(t["D"], a, rtol=1e-12)
+    np.testing.assert_allclose(t["G"], a ** 1.5, rtol=1e-11)
+    ah = 0.5 * (a[:-1] + a[1:])
+    np.testing.assert_allclose(t["kick_a"], (ah ** 1.5 - a[:-1] ** 1.5) / a[:-1], rtol=1e-11)
+    np.testing.assert_allclose(t["drift"], (a[1:] - a[:-1]) / ah ** 1.5, rtol=1e-11)
+    np.testing.assert_allclose(t["kick_b"], (a[1:] ** 1.5 - ah ** 1.5) / a[1:], rtol=1e-11)
+    g2 = api.lpt2_growth(cfg, co)
+    assert abs(g2["D2"] / (-3 / 7 * 0.01) - 1) < 1e-12
+    assert abs(g2["G2"] / (-6 / 7 * 0.1 ** 2.5) - 1) < 1e-11
+    ref = C.kdk_coefficients(1.0, 0.1, 0.9, 8)
+    np.testing.assert_allclose(t["kick_a"], ref.kick_a, rtol=1e-11)
+    assert abs(ref.D20 / g2["D2"] - 1) < 1e-12
