@@ -459,7 +459,7 @@ struct GatherArgs {
 constexpr int gather_threads(int mode) { return mode == kWgrad ? kBlock : 4 * kBlock; }
 
 template <int T, int MODE>
-__global__ void __launch_bounds__(gather_threads(MODE))
+__global__ void __launch_bounds__(gather_threads(MODE), MODE == kWgrad ? 1 : 8)
 k_gather_tile(GatherArgs A, Lattice L, int nt, const uint32_t* __restrict__ offsets) {
     constexpr int NTH = gather_threads(MODE);
     constexpr int NM = MODE == kWgrad ? 1 : 3;
@@ -484,6 +484,35 @@ k_gather_tile(GatherArgs A, Lattice L, int nt, const uint32_t* __restrict__ offs
         const float ic = L.inv_cell;
         for (uint32_t p = pbeg + threadIdx.x; p < pend; p += NTH) {
             uint32_t x[3] = {A.xq[3 * p], A.xq[3 * p + 1], A.xq[3 * p + 2]};
+            // every other input of this particle is loaded before any store: a
+            // load after a store to an array that may alias it would wait a full
+            // memory round trip
+            int32_t pm[3] = {0, 0, 0};
+            float xin[3] = {0.f, 0.f, 0.f}, pin[3] = {0.f, 0.f, 0.f};
+            if constexpr (MODE == kKickDrift) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) pm[a] = A.pq[3 * p + a];
+            } else if constexpr (MODE == kUnkickVjp) {
+                if (A.pq) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) pm[a] = A.pq[3 * p + a];
+                }
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    pin[a] = A.pi_in[3 * p + a];
+                    xin[a] = A.xi[3 * p + a];
+                }
+            } else if constexpr (MODE == kWgrad) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) xin[a] = A.xi[3 * p + a];
+                if (A.flag == 1) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        pm[a] = A.pq[3 * p + a];
+                        pin[a] = A.pi[3 * p + a];
+                    }
+                }
+            }
             int ii[3];
             float t[3];
             locate(x, L, ii, t);
@@ -514,7 +543,7 @@ k_gather_tile(GatherArgs A, Lattice L, int nt, const uint32_t* __restrict__ offs
             if constexpr (MODE == kKickDrift) {
                 int32_t m[3];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) m[a] = A.pq[3 * p + a] + kick_units(A.coeff, F[a], L);
+                for (int a = 0; a < 3; ++a) m[a] = pm[a] + kick_units(A.coeff, F[a], L);
                 if (A.ck_x) {
                     const long q = A.id[p];
 #pragma unroll
@@ -535,26 +564,26 @@ k_gather_tile(GatherArgs A, Lattice L, int nt, const uint32_t* __restrict__ offs
             } else if constexpr (MODE == kUnkickVjp) {
                 if (A.pq) {
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) A.pq[3 * p + a] -= kick_units(A.coeff, F[a], L);
+                    for (int a = 0; a < 3; ++a) A.pq[3 * p + a] = pm[a] - kick_units(A.coeff, F[a], L);
                 }
-                const float pv[3] = {A.pi_in[3 * p], A.pi_in[3 * p + 1], A.pi_in[3 * p + 2]};
+                const float pv[3] = {pin[0], pin[1], pin[2]};
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
-                    A.xi[3 * p + a] += A.coeff * (pv[0] * G[0][a] + pv[1] * G[1][a] + pv[2] * G[2][a]);
+                    A.xi[3 * p + a] = xin[a] + A.coeff * (pv[0] * G[0][a] + pv[1] * G[1][a] + pv[2] * G[2][a]);
                 acc += (double)pv[0] * F[0] + (double)pv[1] * F[1] + (double)pv[2] * F[2];
             } else {   // kWgrad
                 float xv[3];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    xv[a] = A.xi[3 * p + a] + A.coeff * G[0][a];
+                    xv[a] = xin[a] + A.coeff * G[0][a];
                     A.xi[3 * p + a] = xv[a];
                 }
                 if (A.flag == 1) {
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        const int32_t m = A.pq[3 * p + a];
+                        const int32_t m = pm[a];
                         acc += (double)xv[a] * ((double)m * L.mom_unit);
-                        A.pi[3 * p + a] += A.drift * xv[a];
+                        A.pi[3 * p + a] = pin[a] + A.drift * xv[a];
                         A.xq[3 * p + a] = x[a] - drift_units(A.drift, m, L);
                     }
                 }
