@@ -178,7 +178,9 @@ int pm_set_filter(pm_ctx* ctx, const float* weights_dev);
  * scales_host [3*n_steps] multiplies kick_a[0..N-1] | drift[0..N-1] |
  * kick_b[0..N-1] of pm_host_tables (and their Omega_m derivatives); all ones,
  * the default, is plain KDK.  Finite values only.  Reverse-time reconstruction
- * stays exact for any scales.  Invalidates the stored forward run. */
+ * stays exact for any scales.  The scales are kept across pm_set_cosmology and
+ * enter dL/dOmega_m as scale * dfactor/dOmega_m.  Invalidates the stored forward
+ * run. */
 int pm_set_step_scales(pm_ctx* ctx, const double* scales_host);
 
 /* dL/d(scales) [3*n_steps] (same layout) of the last pm_adjoint, i.e. the
