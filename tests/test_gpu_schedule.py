@@ -151,3 +151,16 @@ def test_all_options_together_match_oracle():
     assert out[1][5]["n_checkpoints"] == 3 and max(out[1][5]["ckpt_max_cells"]) == 0.0
     assert rel_l2(out[1][0], out[0][0]) < 1e-4
     assert rel_l2(out[1][4], out[0][4]) < 1e-4
+
+
+def test_step_scales_persist_across_set_cosmology():
+    scales = 1.0 + 0.1 * normal((3, TINY.n_steps), 74)
+    new = replace(CO, omega_m=0.27)
+    a = fresh(TINY)
+    a.set_step_scales(scales)
+    a.set_cosmology(new)
+    b = api.PMContext(api.config_from_workload(TINY), new)
+    b.set_step_scales(scales)
+    n = dev(white_noise(8, 6))
+    for x, y in zip(a.forward(n), b.forward(n)):
+        assert torch.equal(x, y)
