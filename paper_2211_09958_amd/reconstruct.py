@@ -42,6 +42,8 @@ def parse(argv=None):
     p.add_argument("--lr", type=float, default=0.05)
     p.add_argument("--log-every", type=int, default=10)
     p.add_argument("--report", default="")
+    p.add_argument("--lpt-order", type=int, choices=(1, 2), default=1,
+                   help="initial conditions: 1 Zel'dovich, 2 with the 2LPT term")
     return p.parse_args(argv)
 
 
@@ -58,7 +60,8 @@ def cross_correlation(ctx, a, b, n_bins):
 def main(argv=None):
     a = parse(argv)
     dev = torch.device("cuda", torch.cuda.current_device())
-    pm = api.PMContext(api.make_config(a.ptcl, a.mesh, a.box, a.steps), Cosmology(), device=dev)
+    pm = api.PMContext(api.make_config(a.ptcl, a.mesh, a.box, a.steps, lpt_order=a.lpt_order),
+                       Cosmology(), device=dev)
     w_true = torch.as_tensor(white_noise(a.ptcl, a.true_seed), dtype=torch.float32, device=dev)
     _, _, obs = pm.forward(w_true)
     obs = obs.clone()

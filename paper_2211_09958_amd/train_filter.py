@@ -60,6 +60,8 @@ def parse(argv=None):
     p.add_argument("--train", choices=("filter", "schedule", "both"), default="filter",
                    help="what to learn: the force filter, the per-step KDK scales, or both")
     p.add_argument("--lr-schedule", type=float, default=1e-3, help="Adam rate of the step scales")
+    p.add_argument("--lpt-order", type=int, choices=(1, 2), default=1,
+                   help="initial conditions of every run: 1 Zel'dovich, 2 with the 2LPT term")
     p.add_argument("--out-schedule", default="", help="write the step scales (.npy, [3, steps])")
     p.add_argument("--out", default="", help="write the trained weights (.npy, float32)")
     p.add_argument("--report", default="", help="write losses and held-out errors (.json)")
@@ -99,12 +101,13 @@ class Trainer:
         self.dev = torch.device("cuda", torch.cuda.current_device())
         ng = a.ptcl
         self.n_bins = a.n_bins or ng // 2
-        self.coarse = api.PMContext(api.make_config(a.ptcl, ng, a.box, a.steps, filter=True),
-                                    self.cosmo, device=self.dev)
+        lpt = getattr(a, "lpt_order", 1)
+        self.coarse = api.PMContext(api.make_config(a.ptcl, ng, a.box, a.steps, filter=True,
+                                                    lpt_order=lpt), self.cosmo, device=self.dev)
         self.seeds = list(range(a.train_seeds + a.heldout))
         self.noise, self.disp_f, self.pk_f = {}, {}, {}
-        fine = api.PMContext(api.make_config(a.ptcl, a.fine_factor * ng, a.box, a.steps),
-                             self.cosmo, device=self.dev)
+        fine = api.PMContext(api.make_config(a.ptcl, a.fine_factor * ng, a.box, a.steps,
+                                             lpt_order=lpt), self.cosmo, device=self.dev)
         for s in self.seeds:
             self.noise[s] = torch.as_tensor(white_noise(a.ptcl, s), dtype=torch.float32,
                                             device=self.dev)
