@@ -49,6 +49,8 @@ def parse(argv=None):
     p.add_argument("--box", type=float, default=128.0)
     p.add_argument("--steps", type=int, default=31)
     p.add_argument("--train-seeds", type=int, default=56, help="seeds 0..N-1 train")
+    p.add_argument("--first-seed", type=int, default=0,
+                   help="offset of the seed range (training seeds start here)")
     p.add_argument("--heldout", type=int, default=8, help="the next seeds are held out")
     p.add_argument("--batch", type=int, default=8)
     p.add_argument("--epochs", type=int, default=200)
@@ -104,7 +106,8 @@ class Trainer:
         lpt = getattr(a, "lpt_order", 1)
         self.coarse = api.PMContext(api.make_config(a.ptcl, ng, a.box, a.steps, filter=True,
                                                     lpt_order=lpt), self.cosmo, device=self.dev)
-        self.seeds = list(range(a.train_seeds + a.heldout))
+        first = getattr(a, "first_seed", 0)
+        self.seeds = list(range(first, first + a.train_seeds + a.heldout))
         self.noise, self.disp_f, self.pk_f = {}, {}, {}
         fine = api.PMContext(api.make_config(a.ptcl, a.fine_factor * ng, a.box, a.steps,
                                              lpt_order=lpt), self.cosmo, device=self.dev)
