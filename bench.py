@@ -355,12 +355,16 @@ def learned_vs_plain(args, co, noise, disp_plain, plain_value):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    lp.reset_stats()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         dens = step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = P * w.n_steps * args.steps / dt
+    fams = lp.stats()["kernels"]
+    breakdown = {k: round(v["ms"] / args.steps, 1) for k, v in
+                 sorted(fams.items(), key=lambda kv: -kv[1]["ms"]) if v["ms"] > 0}
     half = w.mesh // 4                     # shells with k <= k_Nyq / 2
     pk_ref = lp.power_spectrum(lp.density(disp_plain), w.mesh // 2)[1]
     pk_learned = lp.power_spectrum(dens, w.mesh // 2)[1]
@@ -393,7 +397,7 @@ def learned_vs_plain(args, co, noise, disp_plain, plain_value):
             "reference": "plain 512^3 particles on the 1024^3 mesh, same seed; all P(k) on the "
                          "512^3 mesh",
             "within_2pct": e_l <= 0.02, "weights": os.path.relpath(args.weights, ROOT),
-            "temporal": temporal}
+            "temporal": temporal, "kernel_ms_per_run": breakdown}
 
 
 if __name__ == "__main__":

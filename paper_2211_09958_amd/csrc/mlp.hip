@@ -18,6 +18,13 @@ constexpr int OW1 = 0, OB1 = 128, OW2 = 192, OB2 = 4288, OW3 = 4352, OB3 = 4416,
 
 __device__ __forceinline__ float sigmoid(float z) { return 1.f / (1.f + expf(-z)); }
 
+// Sum over the 64 lanes of a wave (every lane gets the total).
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
 // features of integer |n|^2: |k| / k_Nyq = 2 sqrt(n2) / n
 __device__ __forceinline__ float feature0(long n2, int n) {
     return 2.f * sqrtf((float)n2) / (float)n;
@@ -54,6 +61,9 @@ constexpr int kChunk = 64;   // table entries per tile
 constexpr int kBwdBlocks = 256;
 
 // Block-partial dL/dtheta for dL/df = fbar over the table; partials to scratch.
+// Sums that many lanes add to one parameter are reduced across the wave (output
+// layer) or kept in per-thread registers over the chunks (first layer) and
+// combined once at the end, instead of contended LDS float atomics.
 __global__ void __launch_bounds__(256)
 k_mlp_bwd(const float* __restrict__ theta, int n, float a, long ntab,
           const float* __restrict__ fbar, float* __restrict__ scratch) {
@@ -66,11 +76,15 @@ k_mlp_bwd(const float* __restrict__ theta, int n, float a, long ntab,
     for (int i = tid; i < NPAR; i += 256) th[i] = theta[i];
     for (int i = tid; i < 192; i += 256) g1[i] = 0.f;
     for (int i = tid; i < HID + 1; i += 256) g3[i] = 0.f;
-    // per-thread accumulators: dW2[o][ib*16 .. +16) with o = tid/4, ib = tid%4
+    // per-thread accumulators: dW2[o][ib*16 .. +16) with o = tid/4, ib = tid%4,
+    // and the first-layer terms of hidden units ib .. ib+15 over this thread's entries
     const int o2 = tid >> 2, ib = (tid & 3) * 16;
-    float acc2[16];
+    float acc2[16], acc1[16][3];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc2[k] = 0.f;
+    for (int k = 0; k < 16; ++k) {
+        acc2[k] = 0.f;
+        acc1[k][0] = acc1[k][1] = acc1[k][2] = 0.f;
+    }
     float accb2 = 0.f;
     __syncthreads();
     for (long c0 = (long)blockIdx.x * kChunk; c0 < ntab; c0 += (long)gridDim.x * kChunk) {
@@ -93,10 +107,12 @@ k_mlp_bwd(const float* __restrict__ theta, int n, float a, long ntab,
                 for (int i = 0; i < HID; ++i) z += th[OW2 + o * HID + i] * h1[i];
                 const float sg = sigmoid(z);
                 const float h2 = z * sg;
-                atomicAdd(&g3[o], dg * h2);
+                const float s3 = wave_sum(dg * h2);   // phase A is exactly one wave
+                if (tid == 0) g3[o] += s3;
                 dz2s[tid][o] = dg * th[OW3 + o] * (sg * (1.f + z * (1.f - sg)));
             }
-            if (valid) atomicAdd(&g3[HID], dg);
+            const float sb3 = wave_sum(dg);
+            if (tid == 0) g3[HID] += sb3;
         }
         __syncthreads();
         // phase B: dW2 += dz2^T h1, db2 += sum dz2
@@ -112,7 +128,7 @@ k_mlp_bwd(const float* __restrict__ theta, int n, float a, long ntab,
             const int e = tid >> 2;
             const long ge = c0 + e;
             const float x0 = feature0(ge < ntab ? ge : 0, n), x1 = a;
-#pragma unroll 4
+#pragma unroll
             for (int k = 0; k < 16; ++k) {
                 const int i = ib + k;
                 float dh = 0.f;
@@ -120,13 +136,34 @@ k_mlp_bwd(const float* __restrict__ theta, int n, float a, long ntab,
                 const float z = th[OW1 + 2 * i] * x0 + th[OW1 + 2 * i + 1] * x1 + th[OB1 + i];
                 const float sg = sigmoid(z);
                 const float dz = dh * (sg * (1.f + z * (1.f - sg)));
-                atomicAdd(&g1[2 * i], dz * x0);
-                atomicAdd(&g1[2 * i + 1], dz * x1);
-                atomicAdd(&g1[128 + i], dz);
+                acc1[k][0] += dz * x0;
+                acc1[k][1] += dz * x1;
+                acc1[k][2] += dz;
             }
         }
         __syncthreads();
     }
+    // first layer: sum over the 16 lanes of each wave that share ib (lane bits
+    // 2..5), then one LDS add per (wave, ib) group
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            float v = acc1[k][q];
+#pragma unroll
+            for (int o = 4; o < 64; o <<= 1) v += __shfl_xor(v, o);
+            acc1[k][q] = v;
+        }
+    if ((tid & 63) < 4) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int i = ib + k;
+            atomicAdd(&g1[2 * i], acc1[k][0]);
+            atomicAdd(&g1[2 * i + 1], acc1[k][1]);
+            atomicAdd(&g1[128 + i], acc1[k][2]);
+        }
+    }
+    __syncthreads();
     float* out = scratch + (long)blockIdx.x * NPAR;
 #pragma unroll
     for (int k = 0; k < 16; ++k) out[OW2 + o2 * HID + ib + k] = acc2[k];
