@@ -133,9 +133,12 @@ k_bin_count(const uint32_t* __restrict__ xq, Lattice L, int tile, int nt, long P
         int ii[3];
         float t[3];
         locate(xq + 3 * i, L, ii, t);
-        const uint32_t tix = morton3(ii[0] / tile, ii[1] / tile, ii[2] / tile);
-        uint32_t cls = ((ii[0] % tile == tile - 1) << 2) | ((ii[1] % tile == tile - 1) << 1) |
-                       (ii[2] % tile == tile - 1);
+        // tile is a power of two and ii >= 0: shifts and masks instead of the
+        // (emulated) integer division and remainder by a run-time value
+        const int tl = __ffs(tile) - 1, tm = tile - 1;
+        const uint32_t tix = morton3(ii[0] >> tl, ii[1] >> tl, ii[2] >> tl);
+        uint32_t cls = (((ii[0] & tm) == tm) << 2) | (((ii[1] & tm) == tm) << 1) |
+                       ((ii[2] & tm) == tm);
         key = tix * 8 + cls;
     }
     // one atomic per distinct key in the wave, all issued together: group the
