@@ -312,18 +312,34 @@ k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
         __syncthreads();
         fft_lds<H, E, -1>(v, lds, W, c, j, st);
         __syncthreads();
+        // each lane turns its own elements' dens_k into their contribution (in
+        // the same LDS slot), then the modes n0 and -n0, which share |n|^2, are
+        // added before one atomic per pair
+        const float mult = (k2 == 0 || k2 == n / 2) ? 1.f : 2.f;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = j + e * T;
+            const int n0 = signed_freq(p, n);
+            const int nsq = n0 * n0 + n1 * n1 + k2 * k2;
+            const float2 dk = lds[lpad(p) * W + c];
+            // Re(conj(a) * i dk) = a.y dk.x - a.x dk.y
+            const float fs = nsq > 0 && in_half
+                                 ? mult * (fscale / (float)nsq * (a[e].y * dk.x - a[e].x * dk.y))
+                                 : 0.f;
+            lds[lpad(p) * W + c] = make_float2(fs, 0.f);
+        }
+        __syncthreads();
         if (in_half) {
-            const float mult = (k2 == 0 || k2 == n / 2) ? 1.f : 2.f;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const int n0 = signed_freq(j + e * T, n);
+                const int p = j + e * T;
+                if (p > n / 2) continue;
+                const int n0 = signed_freq(p, n);
                 const int nsq = n0 * n0 + n1 * n1 + k2 * k2;
-                if (nsq > 0) {
-                    const float2 dk = lds[lpad(j + e * T) * W + c];
-                    // Re(conj(a) * i dk) = a.y dk.x - a.x dk.y
-                    const float fs = fscale / (float)nsq * (a[e].y * dk.x - a[e].x * dk.y);
-                    atomicAdd(&fbar[nsq], mult * fs);
-                }
+                if (nsq == 0) continue;
+                float fs = lds[lpad(p) * W + c].x;
+                if (p != 0 && p != n / 2) fs += lds[lpad(n - p) * W + c].x;
+                atomicAdd(&fbar[nsq], fs);
             }
         }
     }
