@@ -30,27 +30,41 @@ __device__ __forceinline__ float feature0(long n2, int n) {
     return 2.f * sqrtf((float)n2) / (float)n;
 }
 
+// One lane per |n|^2 entry.  The hidden layers are streamed: each first-layer
+// unit is computed once and immediately added into the 64 second-layer sums
+// (W2 kept transposed in LDS so that the 64 weights of one input are
+// contiguous), so only the 64 sums stay in registers.  Every sum still runs
+// over its inputs in index order.
 __global__ void __launch_bounds__(256)
 k_mlp_table(const float* __restrict__ theta, int n, float a, float fscale, long ntab,
             float* __restrict__ radial, float* __restrict__ table) {
-    __shared__ float th[NPAR];
-    for (int i = threadIdx.x; i < NPAR; i += 256) th[i] = theta[i];
+    __shared__ float w2t[HID * HID];                 // w2t[i][o] = W2[o][i]
+    __shared__ float th[OW2];                        // W1 | b1
+    __shared__ float tail[NPAR - OB2];               // b2 | W3 | b3
+    for (int k = threadIdx.x; k < HID * HID; k += 256)
+        w2t[(k % HID) * HID + k / HID] = theta[OW2 + k];
+    for (int k = threadIdx.x; k < OW2; k += 256) th[k] = theta[k];
+    for (int k = threadIdx.x; k < NPAR - OB2; k += 256) tail[k] = theta[OB2 + k];
     __syncthreads();
+    const float* b2 = tail;
+    const float* w3 = tail + (OW3 - OB2);
+    const float b3 = tail[OB3 - OB2];
     for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < ntab; e += (long)gridDim.x * 256) {
         const float x0 = feature0(e, n), x1 = a;
-        float h1[HID];
+        float z[HID];
 #pragma unroll
+        for (int o = 0; o < HID; ++o) z[o] = b2[o];
+#pragma unroll 1
         for (int i = 0; i < HID; ++i) {
-            const float z = th[OW1 + 2 * i] * x0 + th[OW1 + 2 * i + 1] * x1 + th[OB1 + i];
-            h1[i] = z * sigmoid(z);
-        }
-        float g = th[OB3];
-        for (int o = 0; o < HID; ++o) {
-            float z = th[OB2 + o];
+            const float z1 = th[OW1 + 2 * i] * x0 + th[OW1 + 2 * i + 1] * x1 + th[OB1 + i];
+            const float h1 = z1 * sigmoid(z1);
+            const float* wr = w2t + i * HID;
 #pragma unroll
-            for (int i = 0; i < HID; ++i) z += th[OW2 + o * HID + i] * h1[i];
-            g += th[OW3 + o] * (z * sigmoid(z));
+            for (int o = 0; o < HID; ++o) z[o] += wr[o] * h1;
         }
+        float g = b3;
+#pragma unroll
+        for (int o = 0; o < HID; ++o) g += w3[o] * (z[o] * sigmoid(z[o]));
         const float f = 1.f + g;
         if (table) table[e] = f;
         if (radial) radial[e] = e == 0 ? 0.f : f * fscale / (float)e;
