@@ -326,3 +326,38 @@ def test_filter_training_resumes_from_its_state(tmp_path):
     assert r["adam_steps"] == 4 and len(r["history"]) == 2
     assert not np.array_equal(a, mlp_init(0, zero_last=True))
     assert np.max(np.abs(a - b)) <= 1e-5 * np.max(np.abs(a))
+
+
+def test_adjoint_repeatable_and_checkpoint_invariant():
+    """Run twice, compare bits: catches LDS races and order-dependent atomics.
+
+    The state and the noise gradient are bitwise repeatable, and so is the
+    noise gradient of a checkpointed adjoint, since the reverse pass rebuilds
+    every checkpointed state exactly.  The parameter sums are FP64 block sums
+    over tiles whose particle order follows the binning atomics, so they repeat
+    to rounding only; the filter gradient is folded with FP32 atomics."""
+    w = SMALL
+    theta = dev(0.3 * mlp_init(1, zero_last=False))
+    noise = dev(white_noise(w.ptcl_grid, 3))
+    g_dens = dev(normal((w.mesh,) * 3, 11) * 1e-3)
+    g_disp = dev(normal((w.ptcl_grid ** 3, 3), 12) * 1e-3)
+    runs = []
+    for ck in (0, 0, 3, 3):
+        cfg = api.make_config(w.ptcl_grid, w.mesh, w.box, w.n_steps, checkpoint_every=ck,
+                              filter=True)
+        pm = api.PMContext(cfg, CO)
+        pm.set_filter(theta)
+        out = pm.forward(noise)
+        g_noise, g_cosmo, g_w = pm.adjoint(g_dens, g_disp, want_filter=True)
+        runs.append((out, g_noise.clone(), np.array(g_cosmo), host(g_w), pm.step_gradients(),
+                     pm.stats()))
+    ref = runs[0]
+    for out, g_noise, g_cosmo, g_w, g_steps, st in runs[1:]:
+        for x, y in zip(out, ref[0]):
+            assert torch.equal(x, y)
+        assert torch.equal(g_noise, ref[1])
+        assert np.allclose(g_cosmo, ref[2], rtol=1e-12, atol=0)
+        assert np.allclose(g_steps, ref[4], rtol=1e-12, atol=1e-12 * np.abs(ref[4]).max())
+        assert rel_l2(g_w, ref[3]) < 1e-5
+        assert st["ic_max_cells"] == 0.0
+    assert max(runs[2][5]["ckpt_max_cells"]) == 0.0
