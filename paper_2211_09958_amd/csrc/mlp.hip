@@ -102,9 +102,12 @@ k_mlp_bwd(const float* __restrict__ theta, int n, float a, long ntab,
     float accb2 = 0.f;
     __syncthreads();
     for (long c0 = (long)blockIdx.x * kChunk; c0 < ntab; c0 += (long)gridDim.x * kChunk) {
-        // phase A: one lane per entry, forward + output layer backward
-        if (tid < kChunk) {
-            const long e = c0 + tid;
+        // phase A: one lane per entry (every wave holds the same 64 entries),
+        // forward + output-layer backward; wave w takes second-layer units
+        // 16w .. 16w+15, so the four waves split the 64 x 64 second layer
+        {
+            const int lane = tid & 63, w = tid >> 6;
+            const long e = c0 + lane;
             const bool valid = e < ntab;
             const float x0 = feature0(valid ? e : 0, n), x1 = a;
             const float dg = valid ? fbar[e] : 0.f;
@@ -113,20 +116,25 @@ k_mlp_bwd(const float* __restrict__ theta, int n, float a, long ntab,
             for (int i = 0; i < HID; ++i) {
                 const float z = th[OW1 + 2 * i] * x0 + th[OW1 + 2 * i + 1] * x1 + th[OB1 + i];
                 h1[i] = z * sigmoid(z);
-                h1s[tid][i] = h1[i];
             }
-            for (int o = 0; o < HID; ++o) {
+            if (w == 0) {
+#pragma unroll
+                for (int i = 0; i < HID; ++i) h1s[lane][i] = h1[i];
+            }
+            for (int o = 16 * w; o < 16 * w + 16; ++o) {
                 float z = th[OB2 + o];
 #pragma unroll
                 for (int i = 0; i < HID; ++i) z += th[OW2 + o * HID + i] * h1[i];
                 const float sg = sigmoid(z);
                 const float h2 = z * sg;
-                const float s3 = wave_sum(dg * h2);   // phase A is exactly one wave
-                if (tid == 0) g3[o] += s3;
-                dz2s[tid][o] = dg * th[OW3 + o] * (sg * (1.f + z * (1.f - sg)));
+                const float s3 = wave_sum(dg * h2);
+                if (lane == 0) g3[o] += s3;
+                dz2s[lane][o] = dg * th[OW3 + o] * (sg * (1.f + z * (1.f - sg)));
             }
-            const float sb3 = wave_sum(dg);
-            if (tid == 0) g3[HID] += sb3;
+            if (w == 0) {
+                const float sb3 = wave_sum(dg);
+                if (lane == 0) g3[HID] += sb3;
+            }
         }
         __syncthreads();
         // phase B: dW2 += dz2^T h1, db2 += sum dz2
