@@ -149,3 +149,18 @@ def test_einstein_de_sitter_host_tables():
     ref = C.kdk_coefficients(1.0, 0.1, 0.9, 8)
     np.testing.assert_allclose(t["kick_a"], ref.kick_a, rtol=1e-11)
     assert abs(ref.D20 / g2["D2"] - 1) < 1e-12
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No fallback: without the built library every call path raises."""
+    monkeypatch.setattr(_lib, "_LIB", None)
+    with pytest.raises(ImportError):
+        _lib.load(str(tmp_path / "libpmx.so"))
+
+
+def test_context_without_a_gpu_fails_loudly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("checks the path taken when no GPU is present")
+    with pytest.raises(RuntimeError):
+        api.PMContext(api.config_from_workload(SMALL), CO)
