@@ -99,6 +99,29 @@ def test_gather_grad_matches_finite_difference():
         np.testing.assert_allclose(an[:, ax], fd, rtol=1e-7, atol=1e-8)
 
 
+def test_gather_grad_is_the_right_derivative_on_node_planes():
+    """At a kink of the CIC weight (a particle exactly on a node plane, t = 0)
+    the gradient is the one-sided derivative from the right: within a cell the
+    interpolant is linear along each axis, so a forward difference reproduces
+    it to rounding, while the backward difference (the other valid one-sided
+    value) differs."""
+    mesh, box = 8, 8.0                          # one cell = 1, nodes at i + 1/2
+    base = np.floor(uniform((40, 3), 33, 0, box))
+    x = base + 0.5 + np.array([0.25, 0.0, 0.6])  # axis 1 exactly on a node plane
+    g = normal((mesh,) * 3, 34)
+    an = M.gather_grad(g, x, box)
+    h = 1e-3
+    f0 = M.gather(g, x, box)
+    for ax in range(3):
+        e = np.zeros(3)
+        e[ax] = h
+        right = (M.gather(g, x + e, box) - f0) / h
+        np.testing.assert_allclose(an[:, ax], right, rtol=1e-9, atol=1e-9)
+    e = np.array([0.0, h, 0.0])
+    left = (f0 - M.gather(g, x - e, box)) / h
+    assert np.max(np.abs(left - an[:, 1])) > 1e-2
+
+
 @pytest.mark.parametrize("ratio", [1, 2])
 def test_unperturbed_lattice_is_uniform(ratio):
     np_, mesh = 8, 8 * ratio
