@@ -44,6 +44,28 @@ def test_ic_mode_amplitudes():
                                atol=1e-12 * np.abs(delta_lin).max())
 
 
+def test_ic_nyquist_reading():
+    """Each displacement component loses the Nyquist plane of its own axis and
+    the k = 0 mode; the other components keep that plane (delta_lin keeps its
+    Nyquist modes)."""
+    np_, box = 8, 32.0
+    s = pm.zeldovich_displacement(white_noise(np_, 2), box, pm.ic_radial(np_, box, CO))
+    n0, n1, n2 = M.wave_integers(np_)
+    nyq = [np.broadcast_to(n0 == -np_ // 2, (np_, np_, np_ // 2 + 1)),
+           np.broadcast_to(n1 == -np_ // 2, (np_, np_, np_ // 2 + 1)),
+           np.broadcast_to(n2 == np_ // 2, (np_, np_, np_ // 2 + 1))]
+    for j in range(3):
+        sk = M.rfftn(s[:, j].reshape(np_, np_, np_))
+        scale = np.abs(sk).max()
+        assert abs(sk[0, 0, 0]) < 1e-13 * scale
+        for a in range(3):
+            on = np.abs(sk[nyq[a]]).max()
+            if a == j:
+                assert on < 1e-13 * scale, (j, a)
+            else:
+                assert on > 1e-3 * scale, (j, a)
+
+
 def test_ic_ensemble_power_matches_linear():
     # mean P(k) of the linear density over seeds ~ P_lin within cosmic variance
     np_, box = 16, 64.0
