@@ -150,6 +150,28 @@ def test_single_mode_force_is_spectrally_exact():
         np.testing.assert_allclose(F[j], -k[j] * np.sin(phase) / k2, atol=1e-12)
 
 
+def test_force_divergence_and_nyquist_reading():
+    """Off every Nyquist plane the force is minus the gradient of the potential:
+    div F = -delta mode by mode.  On the plane n_j = Nyquist only component j
+    is zeroed, so there div F = -delta (1 - k_j^2 / k^2)."""
+    mesh, box = 8, 16.0
+    delta = normal((mesh,) * 3, 35)
+    delta -= delta.mean()
+    F, dk = M.force_meshes(delta, box)
+    n = M.wave_integers(mesh)
+    kf = 2 * np.pi / box
+    div = sum(1j * kf * n[j] * M.rfftn(F[j]) for j in range(3))
+    nsq = n[0] ** 2 + n[1] ** 2 + n[2] ** 2
+    shape = dk.shape
+    nyq = [np.broadcast_to(n[0] == -mesh // 2, shape), np.broadcast_to(n[1] == -mesh // 2, shape),
+           np.broadcast_to(n[2] == mesh // 2, shape)]
+    keep = np.ones(shape)
+    for j in range(3):
+        keep = keep - np.where(nyq[j], np.broadcast_to(n[j] ** 2 / np.where(nsq == 0, 1, nsq), shape), 0.0)
+    want = np.where(np.broadcast_to(nsq == 0, shape), 0.0, -dk * keep)
+    np.testing.assert_allclose(div, want, rtol=0, atol=1e-12 * np.abs(dk).max())
+
+
 def test_force_sums_to_zero_and_no_self_force():
     st = pm.Setup(8, 16, 16.0, 1, None)
     x = uniform((512, 3), 9, 0, 16.0)
