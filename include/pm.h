@@ -51,7 +51,7 @@ typedef enum {
     PM_ENOMEM = -2,   /* workspace too small */
     PM_EHIP = -3,     /* a HIP runtime call failed */
     PM_ESTATE = -4,   /* call order: adjoint without a matching forward, ... */
-    PM_ENUMERIC = -5  /* a non-finite value was produced */
+    PM_ENUMERIC = -5  /* a non-finite value, or one outside the fixed-point range */
 } pm_status;
 
 /* Flat LambdaCDM.  T_cmb <= 0 selects 2.7255 K.  Omega_b and h enter only the
@@ -123,6 +123,10 @@ typedef struct {
     double kernel_ms[PM_NKERNELS];
     int64_t kernel_launches[PM_NKERNELS];
     double kernel_bytes[PM_NKERNELS];
+    /* 1 when a kick of the last pm_forward produced a momentum outside the
+     * int32 fixed-point range (pm_state_units); that run is then invalid and
+     * pm_adjoint returns PM_ENUMERIC. */
+    int32_t momentum_overflow;
 } pm_stats;
 
 typedef struct pm_ctx pm_ctx;
@@ -146,6 +150,15 @@ size_t pm_workspace_bytes(const pm_config* cfg, int* status);
 int pm_host_tables(const pm_config* cfg, const pm_cosmology* cosmo,
                    double* coeffs_host, double* dcoeffs_host,
                    double* growth_host, double* pk_host);
+
+/* Fixed-point units of the particle state for this config (host only, no GPU):
+ * out_host[3] = {position unit box/2^32 (Mpc/h), momentum unit, momentum range
+ * 2^31 * unit}.  The momentum unit is cell * 2^-22, doubled while the range is
+ * below 100 Mpc/h per unit time (canonical momentum p = a^2 dx/dt with H0 = 1,
+ * i.e. 10^4 km/s of peculiar velocity at a = 1).  A forward kick that would
+ * leave the range is detected on the GPU: pm_stats_get reports it and
+ * pm_adjoint returns PM_ENUMERIC. */
+int pm_state_units(const pm_config* cfg, double* out_host);
 
 /* Second-order growth of the 2LPT initial conditions at a_0 = a_start (host
  * only, no GPU): out_host[4] = {D2(a_0), G2(a_0), dD2/dOmega_m, dG2/dOmega_m}
@@ -295,7 +308,7 @@ int pm_adam(pm_ctx* ctx, float* param_dev, const float* grad_dev, int32_t n_grad
             float* m_dev, float* v_dev, int32_t n, double lr, double beta1,
             double beta2, double eps, int32_t t);
 
-/* Statistics of the context; synchronises the stream when PM_F_TIMING is set.
+/* Statistics of the context; synchronises the stream.
  * pm_stats_reset clears the per-kernel accumulators. */
 int pm_stats_get(pm_ctx* ctx, pm_stats* out);
 int pm_stats_reset(pm_ctx* ctx);

@@ -23,8 +23,8 @@ KERNEL_FAMILIES = ("bin", "scatter", "scatter_vec", "fft_x", "fft_strided", "gra
                    "grad_adj_z", "gather", "unkick_vjp", "wgrad", "mlp", "other")
 
 # exported entry points, in the order include/pm.h declares them
-EXPORTS = ("pm_workspace_bytes", "pm_host_tables", "pm_init", "pm_set_cosmology",
-           "pm_set_filter", "pm_forward", "pm_adjoint", "pm_loss_mse", "pm_loss_pk",
+EXPORTS = ("pm_workspace_bytes", "pm_host_tables", "pm_state_units", "pm_init",
+           "pm_set_cosmology", "pm_set_filter", "pm_forward", "pm_adjoint", "pm_loss_mse", "pm_loss_pk",
            "pm_loss_disp", "pm_power_spectrum",
            "pm_density", "pm_force", "pm_force_vjp", "pm_fft_r2c", "pm_fft_c2r",
            "pm_lpt2_growth", "pm_initial_conditions", "pm_set_step_scales",
@@ -53,7 +53,8 @@ class Stats(ctypes.Structure):
                 ("ic_mom_rel_rms", c_double), ("workspace_bytes", c_size_t),
                 ("kernel_ms", c_double * len(KERNEL_FAMILIES)),
                 ("kernel_launches", ctypes.c_int64 * len(KERNEL_FAMILIES)),
-                ("kernel_bytes", c_double * len(KERNEL_FAMILIES))]
+                ("kernel_bytes", c_double * len(KERNEL_FAMILIES)),
+                ("momentum_overflow", c_int32)]
 
 
 class PMError(RuntimeError):
@@ -77,6 +78,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     sig = {
         "pm_workspace_bytes": (c_size_t, [POINTER(Config), POINTER(c_int)]),
         "pm_host_tables": (c_int, [POINTER(Config), POINTER(Cosmology), P, P, P, P]),
+        "pm_state_units": (c_int, [POINTER(Config), P]),
         "pm_init": (c_int, [POINTER(Config), POINTER(Cosmology), P, c_size_t, P, POINTER(P)]),
         "pm_set_cosmology": (c_int, [P, POINTER(Cosmology)]),
         "pm_set_filter": (c_int, [P, P]),

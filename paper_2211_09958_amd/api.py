@@ -69,6 +69,15 @@ def host_tables(cfg: Config, cosmo):
             "D": gr[:N + 1], "dD": gr[N + 1:2 * N + 2], "G": gr[2 * N + 2:], "pk": pk}
 
 
+def state_units(cfg: Config):
+    """Fixed-point units of the particle state (no GPU): position unit, momentum
+    unit and momentum range (the largest representable |p|)."""
+    import numpy as np
+    out = np.zeros(3)
+    check(_lib.load().pm_state_units(byref(cfg), out.ctypes.data_as(c_void_p)))
+    return {"position_unit": out[0], "momentum_unit": out[1], "momentum_range": out[2]}
+
+
 def lpt2_growth(cfg: Config, cosmo):
     """Second-order growth at a_start (no GPU): D2, G2 and their Omega_m derivatives."""
     import numpy as np
@@ -99,6 +108,9 @@ class PMContext:
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             self.stream = torch.cuda.current_stream(self.device)
         self.ctx = c_void_p()
+        # number of pm_forward calls on this context: the adjoint differentiates
+        # the most recent one, so an autograd graph remembers which run it owns
+        self.forward_count = 0
         check(self.lib.pm_init(byref(cfg), byref(self._cosmo), _ptr(self.workspace), nbytes,
                                c_void_p(self.stream.cuda_stream), byref(self.ctx)))
 
@@ -146,6 +158,7 @@ class PMContext:
         noise = self._in(noise, (self.np,) * 3)
         disp, mom = self._vec(), self._vec()
         dens = self._mesh() if want_density else None
+        self.forward_count += 1
         self._check(self.lib.pm_forward(self.ctx, _ptr(noise), _ptr(disp), _ptr(mom), _ptr(dens)))
         return disp, mom, dens
 
@@ -293,7 +306,8 @@ class PMContext:
                 "n_checkpoints": n, "ckpt_rms_cells": list(s.ckpt_rms_cells[:n]),
                 "ckpt_max_cells": list(s.ckpt_max_cells[:n]),
                 "ic_rms_cells": s.ic_rms_cells, "ic_max_cells": s.ic_max_cells,
-                "ic_mom_rel_rms": s.ic_mom_rel_rms, "workspace_bytes": s.workspace_bytes}
+                "ic_mom_rel_rms": s.ic_mom_rel_rms, "workspace_bytes": s.workspace_bytes,
+                "momentum_overflow": bool(s.momentum_overflow)}
 
 
 class Simulate(torch.autograd.Function):
@@ -301,7 +315,8 @@ class Simulate(torch.autograd.Function):
 
     forward calls pm_forward; backward calls pm_adjoint (the reverse-time
     adjoint), returning dL/dnoise, dL/dOmega_m, dL/dsigma_8, dL/dweights and
-    dL/d(step scales).  omega_m and sigma8 are 0-d tensors (their values update
+    dL/d(step scales).  The context keeps one forward run, so backward raises if
+    the context ran another forward after this graph was built.  omega_m and sigma8 are 0-d tensors (their values update
     the context's cosmology when they change); weights may be None for the plain
     force; step_scales ([3, n_steps] multipliers of kick_a, drift, kick_b) may be
     None for plain KDK.
@@ -319,6 +334,7 @@ class Simulate(torch.autograd.Function):
             pm.set_step_scales(step_scales.detach().double().cpu().numpy())
         disp, mom, dens = pm.forward(noise.detach().contiguous())
         fctx.pm = pm
+        fctx.run = pm.forward_count
         fctx.has_w = weights is not None
         fctx.scales = None if step_scales is None else (step_scales.shape, step_scales.dtype,
                                                         step_scales.device)
@@ -328,6 +344,10 @@ class Simulate(torch.autograd.Function):
     @staticmethod
     def backward(fctx, g_disp, g_mom, g_dens):
         pm = fctx.pm
+        if pm.forward_count != fctx.run:
+            raise RuntimeError("the PMContext ran another forward after this graph was built; "
+                               "pm_adjoint only differentiates the most recent run (use one "
+                               "context per graph, or call backward before the next simulate)")
         c = lambda t: None if t is None else t.contiguous()
         g_noise, (g_om, g_s8), g_w = pm.adjoint(c(g_dens), c(g_disp), c(g_mom), want_filter=fctx.has_w)
         dev = fctx.dev

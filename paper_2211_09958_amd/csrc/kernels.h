@@ -62,7 +62,8 @@ void launch_fft3_c2r(float2* buf, int n, int cs, int nbuf, long bufStride, const
 // Particle state is fixed point so that kick and drift are exactly invertible:
 // positions x are uint32 in units of box / 2^32 (periodic wrap is integer
 // overflow; a mesh cell is 2^shift units), momenta are int32 in units of
-// mom_unit = cell * 2^-22 (range +-512 cells per unit time).
+// mom_unit = cell * 2^-22, coarsened by powers of two for small cells so that the
+// range 2^31 mom_unit covers |p| <= 100 Mpc/h per unit time (state_units).
 struct Lattice {
     int np;            // particles per side
     int ng;            // mesh cells per side
@@ -125,11 +126,12 @@ void launch_scatter_vec(const uint32_t* xq, const float* v, float coeff, unsigne
 // sorted by those bins); partials (nullable) get one FP64 value per tile.
 long gather_blocks(const Bins& b);
 // F = gather(force meshes), p += kick F, optional checkpoint copy of (x, p) in
-// lattice order (by id), then x += drift p (if do_drift).
+// lattice order (by id), then x += drift p (if do_drift).  *ovf (nullable) is
+// set to 1 when a new momentum does not fit the int32 fixed-point range.
 void launch_gather_kick_drift(uint32_t* xq, int32_t* pq, const uint32_t* id, const float* fmesh,
                               long fStride, const Lattice& L, const Bins& b, float kick,
                               float drift, int do_drift, uint32_t* ck_x, int32_t* ck_p,
-                              hipStream_t s);
+                              unsigned* ovf, hipStream_t s);
 // out[id[p]][j] = Sum w F_j (lattice order).
 void launch_gather_force(const uint32_t* xq, const uint32_t* id, const float* fmesh, long fStride,
                          const Lattice& L, const Bins& b, float* out, hipStream_t s);
@@ -242,5 +244,8 @@ long mlp_backward_scratch(int n);
 void launch_adam(float* p, const float* g, int ngrad, float* m, float* v, int n, float lr,
                  float b1, float b2, float eps, float bc1, float bc2, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
+
+// Message returned by pm_last_error(NULL) (calls without a context).
+void set_context_free_error(const char* msg);
 
 }  // namespace pmx

@@ -79,9 +79,14 @@ __device__ __forceinline__ void locate(const uint32_t* __restrict__ x3, const La
     }
 }
 
+// Momentum increment of a kick by coeff * F in integer units, before rounding.
+__device__ __forceinline__ float kick_raw(float coeff, float F, const Lattice& L) {
+    return __fmul_rn(__fmul_rn(coeff, F), L.inv_mom_unit);
+}
+
 // Integer momentum increment of a kick by coeff * F (forward adds, reverse subtracts).
 __device__ __forceinline__ int32_t kick_units(float coeff, float F, const Lattice& L) {
-    return __float2int_rn(__fmul_rn(__fmul_rn(coeff, F), L.inv_mom_unit));
+    return __float2int_rn(kick_raw(coeff, F, L));
 }
 
 // Integer position increment of a drift by coeff * p, wrapped modulo the box.
@@ -454,6 +459,7 @@ struct GatherArgs {
     float* xi;            // kUnkickVjp, kWgrad
     float* pi;            // kWgrad
     double* partials;     // one per tile (nullable)
+    unsigned* ovf;        // kKickDrift: set to 1 when a momentum leaves the int32 range
 };
 
 // Threads per gather work-group: the three-mesh tile takes 59 KB of LDS (two
@@ -544,9 +550,18 @@ k_gather_tile(GatherArgs A, Lattice L, int nt, const uint32_t* __restrict__ offs
                 }
             }
             if constexpr (MODE == kKickDrift) {
+                // p + increment in 64 bits: a sum or an increment outside the int32
+                // range (or a non-finite force) would wrap silently, so it is flagged
                 int32_t m[3];
+                bool bad = false;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) m[a] = pm[a] + kick_units(A.coeff, F[a], L);
+                for (int a = 0; a < 3; ++a) {
+                    const float q = kick_raw(A.coeff, F[a], L);
+                    const long long sum = (long long)pm[a] + __float2int_rn(q);
+                    m[a] = (int32_t)sum;
+                    bad = bad || !(fabsf(q) < 2.0e9f) || sum != (long long)m[a];
+                }
+                if (bad && A.ovf) atomicOr(A.ovf, 1u);
                 if (A.ck_x) {
                     const long q = A.id[p];
 #pragma unroll
@@ -1138,8 +1153,9 @@ long gather_blocks(const Bins& b) { return (long)b.nt * b.nt * b.nt; }
 void launch_gather_kick_drift(uint32_t* xq, int32_t* pq, const uint32_t* id, const float* fmesh,
                               long fStride, const Lattice& L, const Bins& b, float kick,
                               float drift, int do_drift, uint32_t* ck_x, int32_t* ck_p,
-                              hipStream_t s) {
+                              unsigned* ovf, hipStream_t s) {
     GatherArgs A{};
+    A.ovf = ovf;
     A.xq = xq;
     A.pq = pq;
     A.id = id;

@@ -81,6 +81,20 @@ Cosmo to_cosmo(const pm_cosmology* c) {
     return Cosmo{c->omega_m, c->omega_b, c->h, c->sigma8, c->n_s, c->T_cmb > 0 ? c->T_cmb : 2.7255};
 }
 
+// Fixed-point units of the particle state: positions in box / 2^32 (periodic wrap
+// is integer overflow); momenta in cell * 2^-22, doubled while the int32 range
+// 2^31 units falls short of kMomBound, so that |p| <= kMomBound Mpc/h per unit
+// time (10^4 km/s of peculiar velocity at a = 1, far above cluster velocities)
+// is representable at any cell size.
+constexpr double kMomBound = 100.0;
+
+void state_units(const pm_config& c, double* pos, double* mom) {
+    *pos = c.box / 4294967296.0;
+    double u = c.box / c.mesh * std::ldexp(1.0, -22);
+    while (u * 2147483648.0 < kMomBound) u *= 2.0;
+    *mom = u;
+}
+
 int n_checkpoints(const pm_config& c) {
     return c.checkpoint_every > 0 ? (c.n_steps - 1) / c.checkpoint_every : 0;
 }
@@ -93,7 +107,7 @@ struct Plan {
     size_t counts, offsets, keys, ranks, scan_tmp;
     size_t radial_f, radial_ic, radial_ic_dom, radial_lpt, losstab, tw, tw_stages, partials, sums, maxbits,
         pkbins;
-    size_t theta, gtheta, fbar, mlp_scratch;
+    size_t theta, gtheta, fbar, mlp_scratch, ovf;
     long cplx_elems, P, nkeys, ntab_f, ntab_p;
     int cs, cs_p, tile, nt, nckpt;
 
@@ -153,10 +167,15 @@ struct Plan {
         gtheta = take(kNParam * sizeof(float));
         fbar = take(c.filter ? ntab_f * sizeof(float) : 0);
         mlp_scratch = take(c.filter ? mlp_backward_scratch(ng) * sizeof(float) : 0);
+        ovf = take(sizeof(unsigned));
     }
 };
 
 }  // namespace
+
+namespace pmx {
+void set_context_free_error(const char* msg) { g_err = msg; }
+}  // namespace pmx
 
 struct pm_ctx {
     pm_config cfg;
@@ -187,6 +206,7 @@ struct pm_ctx {
     Twiddles twd;
     double *partials, *sums, *pkbins;
     unsigned* maxbits;
+    unsigned* ovf;                  // set by the forward kicks on a momentum overflow
     Schedule sched, dsched;         // KDK factors in use (scaled) and their d/dOmega_m
     Schedule sched0;                // the unscaled growth-factor schedule
     std::vector<double> step_scale; // [3N] multipliers of kick_a | drift | kick_b
@@ -623,6 +643,22 @@ int pm_host_tables(const pm_config* cfg, const pm_cosmology* cosmo, double* coef
     return PM_OK;
 }
 
+int pm_state_units(const pm_config* cfg, double* out) {
+    std::string why;
+    int rc = check_config(cfg, &why);
+    if (rc == PM_OK && !out) {
+        why = "out is required";
+        rc = PM_EINVAL;
+    }
+    if (rc != PM_OK) {
+        g_err = why;
+        return rc;
+    }
+    state_units(*cfg, &out[0], &out[1]);
+    out[2] = out[1] * 2147483648.0;
+    return PM_OK;
+}
+
 int pm_lpt2_growth(const pm_config* cfg, const pm_cosmology* cosmo, double* out) {
     std::string why;
     int rc = check_config(cfg, &why);
@@ -710,6 +746,7 @@ int pm_init(const pm_config* cfg, const pm_cosmology* cosmo, void* workspace, si
     ctx->gtheta = ctx->at<float>(p.gtheta);
     ctx->fbar = ctx->at<float>(p.fbar);
     ctx->mlp_scratch = ctx->at<float>(p.mlp_scratch);
+    ctx->ovf = ctx->at<unsigned>(p.ovf);
     {
         Lattice& L = ctx->lat;
         int lg = 0;
@@ -725,8 +762,10 @@ int pm_init(const pm_config* cfg, const pm_cosmology* cosmo, void* workspace, si
         L.frac = (float)std::ldexp(1.0, -L.shift);
         L.len_to_pos = (float)(4294967296.0 / cfg->box);
         L.pos_to_len = (float)(cfg->box / 4294967296.0);
-        L.mom_unit = (float)(cfg->box / ctx->ng * std::ldexp(1.0, -22));
-        L.inv_mom_unit = (float)(1.0 / ((double)cfg->box / ctx->ng * std::ldexp(1.0, -22)));
+        double pos_unit, mom_unit;
+        state_units(*cfg, &pos_unit, &mom_unit);
+        L.mom_unit = (float)mom_unit;
+        L.inv_mom_unit = (float)(1.0 / mom_unit);
     }
     ctx->bins.tile = p.tile;
     ctx->bins.nt = p.nt;
@@ -756,6 +795,7 @@ int pm_init(const pm_config* cfg, const pm_cosmology* cosmo, void* workspace, si
     rc = upload_tables(ctx);
     if (rc == PM_OK) {
         launch_zero(ctx->theta, kNParam * sizeof(float), ctx->stream);
+        launch_zero(ctx->ovf, sizeof(unsigned), ctx->stream);
         rc = ctx->hip_check("pm_init");
     }
     if (rc != PM_OK) {
@@ -815,6 +855,9 @@ int pm_forward(pm_ctx* ctx, const float* noise, float* disp_out, float* mom_out,
     PM_TRY(ctx_check(ctx));
     if (!noise || !disp_out || !mom_out) return ctx->fail(PM_EINVAL, "noise, disp and mom are required");
     if (ctx->cfg.filter && !ctx->have_filter) return ctx->fail(PM_ESTATE, "pm_set_filter not called");
+    // the stored run is overwritten from here on: valid again only once the whole
+    // new run has been enqueued without error
+    ctx->have_forward = false;
     ctx->have_step_grads = false;
     hipStream_t s = ctx->stream;
     const pm_config& c = ctx->cfg;
@@ -822,6 +865,7 @@ int pm_forward(pm_ctx* ctx, const float* noise, float* disp_out, float* mom_out,
     const int N = c.n_steps;
     (void)hipEventRecord(ctx->ev[0], s);
     PM_TRY(copy_d2d(ctx, ctx->noise, noise, (size_t)ctx->P * sizeof(float)));
+    launch_zero(ctx->ovf, sizeof(unsigned), s);
     if (ctx->lpt2()) lpt_second_order(ctx, ctx->noise, ctx->tmpv);
     ic_synthesis(ctx, ctx->noise, ctx->radial_ic, ctx->s_ic, ctx->xq, ctx->pq, ctx->id,
                  ctx->lpt2() ? ctx->tmpv : nullptr);
@@ -838,7 +882,7 @@ int pm_forward(pm_ctx* ctx, const float* noise, float* disp_out, float* mom_out,
         KTimer t(ctx, PM_K_GATHER, (ckx ? 72.0 : 48.0) * ctx->P + 3 * mesh_r(ctx->ng));
         launch_gather_kick_drift(ctx->xq, ctx->pq, ctx->id, ctx->creal(1), ctx->creal_stride(),
                                  ctx->lat, ctx->bins, (float)kick,
-                                 n < N ? (float)sc.drift[n] : 0.f, n < N, ckx, ckp, s);
+                                 n < N ? (float)sc.drift[n] : 0.f, n < N, ckx, ckp, ctx->ovf, s);
     }
     {
         KTimer t(ctx, PM_K_OTHER, 0);
@@ -1004,10 +1048,15 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
     const int nsum = 2 * N + 1 + kExtraSlots;
     std::vector<double> h(nsum);
     std::vector<unsigned> mb(kExtraSlots);
+    unsigned ovf = 0;
     if (hipMemcpyAsync(h.data(), ctx->sums, nsum * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipMemcpyAsync(mb.data(), ctx->maxbits, kExtraSlots * sizeof(unsigned), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&ovf, ctx->ovf, sizeof(unsigned), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return ctx->fail(PM_EHIP, "reading adjoint sums failed");
+    if (ovf)
+        return ctx->fail(PM_ENUMERIC, "a momentum of the forward run left the fixed-point range "
+                                      "(see pm_state_units)");
     const Schedule& d = ctx->dsched;
     double g_om = 0.0;
     for (int n = 0; n < N; ++n)
@@ -1276,6 +1325,11 @@ int pm_stats_get(pm_ctx* ctx, pm_stats* out) {
         ctx->stats.forward_ms = ms;
     ctx->flush_timing();
     (void)hipGetLastError();
+    unsigned ovf = 0;
+    if (hipMemcpyAsync(&ovf, ctx->ovf, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return ctx->fail(PM_EHIP, "reading the overflow flag failed");
+    ctx->stats.momentum_overflow = ovf ? 1 : 0;
     *out = ctx->stats;
     return PM_OK;
 }

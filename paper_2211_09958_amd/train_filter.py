@@ -56,7 +56,8 @@ def parse(argv=None):
     p.add_argument("--epochs", type=int, default=200)
     p.add_argument("--lr", type=float, default=1e-3)
     p.add_argument("--w-disp", type=float, default=1e-2, help="weight of the position loss")
-    p.add_argument("--n-bins", type=int, default=0, help="P(k) shells in the loss (0: Ng/2)")
+    p.add_argument("--n-bins", type=int, default=0,
+                   help="P(k) shells in the loss (0: Ng/4, the shells up to k_Nyq/2)")
     p.add_argument("--init-seed", type=int, default=0)
     p.add_argument("--init", default="", help="start from these weights (.npy) instead")
     p.add_argument("--train", choices=("filter", "schedule", "both"), default="filter",
@@ -102,7 +103,8 @@ class Trainer:
         self.cosmo = cosmo or Cosmology()
         self.dev = torch.device("cuda", torch.cuda.current_device())
         ng = a.ptcl
-        self.n_bins = a.n_bins or ng // 2
+        # the 2 % criterion is judged on k <= k_Nyq/2, i.e. shells |n| <= Ng/4
+        self.n_bins = a.n_bins or ng // 4
         lpt = getattr(a, "lpt_order", 1)
         self.coarse = api.PMContext(api.make_config(a.ptcl, ng, a.box, a.steps, filter=True,
                                                     lpt_order=lpt), self.cosmo, device=self.dev)

@@ -44,3 +44,47 @@ def periodic_cells(a, b, box, mesh):
     d = np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)
     d -= box * np.round(d / box)
     return np.sqrt(np.sum(d * d, axis=1)) * mesh / box
+
+
+def oracle_gradients(w, seed_run, seed_tgt, theta=None, noise_pert=0.0, lpt_order=1):
+    """Oracle gradients of the MSE loss against the final density of seed_tgt
+    plus seeded displacement and momentum cotangents (1e-3 N(0,1)); with
+    noise_pert > 0 the run's noise is multiplied by (1 + noise_pert xi), xi a
+    seeded N(0,1) field.  Returns (noise, target, gdisp, gmom, gradients, run)."""
+    from synthetic import normal, white_noise
+    st = setup_for(w, lpt_order)
+    noise = white_noise(w.ptcl_grid, seed_run)
+    if noise_pert:
+        noise = noise * (1.0 + noise_pert * normal(noise.shape, 99))
+    target = opm.forward(white_noise(w.ptcl_grid, seed_tgt), st).dens
+    run = opm.forward(noise, st, theta)
+    _, gd = opm.mse_loss(run.dens, target)
+    P = w.ptcl_grid ** 3
+    gdisp, gmom = normal((P, 3), 9) * 1e-3, normal((P, 3), 10) * 1e-3
+    ref = opm.adjoint(run, noise, g_dens=gd, g_disp=gdisp, g_mom=gmom)
+    return noise, target, gdisp, gmom, ref, run
+
+
+def gradient_envelope(w, seed_run, seed_tgt, ref, run, theta=None, pert=1e-6):
+    """How far the oracle's own gradients move when the input noise is perturbed
+    at the size of single-precision rounding.
+
+    CIC weights are piecewise linear, so the force Jacobian jumps whenever a
+    particle crosses a mesh node plane; two trajectories that differ by rounding
+    (FP32 vs FP64: about 1e-5 cells RMS at a = 1 on the 32^3 / 64^3 workload)
+    take different sides of some of those jumps, and their exact gradients
+    differ by more than rounding.  A relative perturbation of 1e-6 of the noise
+    moves the oracle's final positions by the same ~1e-5 cells; the relative
+    change of each gradient under it is returned, so a parity bar of
+    max(1e-3, 3 x envelope) asks the GPU to be as close to the oracle as the
+    oracle is to itself.  Returns (dict of relative changes, RMS position
+    change in cells).  ref and run are the unperturbed oracle_gradients results."""
+    _, _, _, _, alt, run_alt = oracle_gradients(w, seed_run, seed_tgt, theta, noise_pert=pert)
+    d = periodic_cells(run_alt.disp[-1], run.disp[-1], w.box, w.mesh)
+    env = {"noise": rel_l2(alt.noise, ref.noise),
+           "omega_m": abs(alt.omega_m / ref.omega_m - 1),
+           "sigma8": abs(alt.sigma8 / ref.sigma8 - 1)}
+    if theta is not None:
+        env["theta"] = rel_l2(alt.theta, ref.theta)
+    return env, float(np.sqrt(np.mean(d * d)))
+

@@ -9,7 +9,7 @@ import pytest
 from oracle import cosmology as C
 from oracle import pm as opm
 from paper_2211_09958_amd import _lib, api
-from synthetic import SMALL, LARGE, MEDIUM, Cosmology
+from synthetic import LARGE, MEDIUM, SMALL, WORKLOADS, Cosmology
 
 CO = Cosmology()
 
@@ -71,6 +71,26 @@ def test_workspace_scales_with_mesh_not_steps():
     assert 0 <= b - a < 1 << 20   # reverse-time adjoint: only scalar slots grow with steps
     big = api.workspace_bytes(api.config_from_workload(LARGE))
     assert big < 60e9
+
+
+def test_state_units_cover_the_momentum_bound():
+    """Momenta are int32 multiples of cell * 2^-22, coarsened by powers of two
+    for small cells until the range covers |p| <= 100 Mpc/h per unit time."""
+    u = api.state_units(api.config_from_workload(LARGE))          # cell 0.5
+    assert u["position_unit"] == 512.0 / 2 ** 32
+    assert u["momentum_unit"] == 0.5 * 2.0 ** -22 and u["momentum_range"] == 256.0
+    for w in WORKLOADS.values():
+        r = api.state_units(api.config_from_workload(w))
+        assert r["momentum_range"] >= 100.0
+        assert r["momentum_unit"] == w.cell * 2.0 ** -22 or r["momentum_range"] < 200.0
+    tiny = api.state_units(api.make_config(64, 1024, 64.0, 10))    # cell 1/16: range 32 by default
+    assert 100.0 <= tiny["momentum_range"] < 200.0
+    ratio = tiny["momentum_unit"] / (64.0 / 1024 * 2.0 ** -22)
+    assert ratio == 4.0
+    cfg = api.config_from_workload(SMALL)
+    cfg.mesh = 12
+    with pytest.raises(_lib.PMError):
+        api.state_units(cfg)
 
 
 @pytest.mark.parametrize("w", [SMALL, MEDIUM])

@@ -3,7 +3,8 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import CO, context, ctx_for, dev, host, periodic_cells, rel_l2, setup_for
+from gpu_util import (CO, context, ctx_for, dev, gradient_envelope, host, oracle_gradients,
+                      periodic_cells, rel_l2, setup_for)
 from oracle import mesh as M
 from oracle import mlp as omlp
 from oracle import pm as opm
@@ -58,18 +59,6 @@ def test_forward_bitwise_repeatable():
         assert torch.equal(x, y)
 
 
-def _grad_case(w, seed_run, seed_tgt, theta=None):
-    st = setup_for(w)
-    noise = white_noise(w.ptcl_grid, seed_run)
-    target = opm.forward(white_noise(w.ptcl_grid, seed_tgt), st).dens
-    run = opm.forward(noise, st, theta)
-    _, gd = opm.mse_loss(run.dens, target)
-    P = w.ptcl_grid ** 3
-    gdisp, gmom = normal((P, 3), 9) * 1e-3, normal((P, 3), 10) * 1e-3
-    ref = opm.adjoint(run, noise, g_dens=gd, g_disp=gdisp, g_mom=gmom)
-    return noise, target, gdisp, gmom, ref
-
-
 def omega_m_scale(w, ref):
     """Sum of |terms| of dL/dOmega_m in the oracle's decomposition."""
     from oracle import cosmology as C
@@ -83,7 +72,7 @@ def omega_m_scale(w, ref):
 
 @pytest.mark.parametrize("w", [TINY, SMALL])
 def test_gradients_match_oracle(w):
-    noise, target, gdisp, gmom, ref = _grad_case(w, 3, 4)
+    noise, target, gdisp, gmom, ref, run = oracle_gradients(w, 3, 4)
     pm = ctx_for(w)
     disp, mom, dens = pm.forward(dev(noise))
     L, gd = pm.loss_mse(dens, dev(target))
@@ -93,9 +82,19 @@ def test_gradients_match_oracle(w):
     # with the sum of their magnitudes, so the error is measured against it
     e_om = abs(g_om - ref.omega_m) / omega_m_scale(w, ref)
     e_s8 = abs(g_s8 / ref.sigma8 - 1)
-    print(f"{w.name}: noise {e_noise:.2e} Om {e_om:.2e} (plain rel "
-          f"{abs(g_om / ref.omega_m - 1):.2e}) s8 {e_s8:.2e}")
+    e_om_plain = abs(g_om / ref.omega_m - 1)
+    print(f"{w.name}: noise {e_noise:.2e} Om {e_om:.2e} (plain rel {e_om_plain:.2e}) "
+          f"s8 {e_s8:.2e}")
     assert e_noise < 1e-3 and e_om < 1e-3 and e_s8 < 1e-3
+    if w is SMALL:
+        # the 32^3 / 64^3 workload against plain relative bars: 1e-3, or three
+        # times the oracle's own envelope where the trajectory's CIC kinks make
+        # the exact gradient move more than that under FP32-sized perturbations
+        env, dpos = gradient_envelope(w, 3, 4, ref, run)
+        print(f"oracle envelope {env} (positions moved {dpos:.1e} cells)")
+        assert e_noise < max(1e-3, 3 * env["noise"])
+        assert e_om_plain < max(1e-3, 3 * env["omega_m"])
+        assert e_s8 < max(1e-3, 3 * env["sigma8"])
 
 
 @pytest.mark.parametrize("w", [TINY, SMALL])
@@ -113,7 +112,7 @@ def test_reverse_time_reconstruction(w):
 
 def test_checkpointed_adjoint_matches_pure():
     w = SMALL
-    noise, target, gdisp, gmom, ref = _grad_case(w, 5, 6)
+    noise, target, gdisp, gmom, ref, run = oracle_gradients(w, 5, 6)
     out = []
     for ck in (0, 3):
         pm = context(w.ptcl_grid, w.mesh, w.box, w.n_steps, checkpoint_every=ck)
@@ -126,6 +125,16 @@ def test_checkpointed_adjoint_matches_pure():
             assert max(st["ckpt_max_cells"]) == 0.0
     assert rel_l2(host(out[1][0]), host(out[0][0])) < 1e-4
     assert abs(out[1][1][0] / out[0][1][0] - 1) < 1e-4
+    # and both against the oracle's stored-trajectory adjoint, to the oracle's
+    # own envelope under FP32-sized input perturbations (gradient_envelope)
+    env, dpos = gradient_envelope(w, 5, 6, ref, run)
+    bar = {k: max(1e-3, 3 * v) for k, v in env.items()}
+    for g_noise, (g_om, g_s8), _ in out:
+        e = {"noise": rel_l2(host(g_noise), ref.noise), "omega_m": abs(g_om / ref.omega_m - 1),
+             "sigma8": abs(g_s8 / ref.sigma8 - 1)}
+        print(f"errors {e}; oracle envelope {env} (positions moved {dpos:.1e} cells)")
+        for k in e:
+            assert e[k] < bar[k], (k, e[k], bar[k])
 
 
 def test_autograd_function():
@@ -141,6 +150,23 @@ def test_autograd_function():
     ref = opm.adjoint(run, white_noise(8, 2), g_dens=2 * run.dens / run.dens.size)
     assert rel_l2(host(noise.grad), ref.noise) < 1e-3
     assert abs(float(om.grad) / ref.omega_m - 1) < 1e-3
+
+
+def test_autograd_rejects_a_stale_graph():
+    """The context keeps one forward run: backward of a graph whose run was
+    replaced by a later simulate() on the same context must raise, not return the
+    later run's gradients."""
+    pm = ctx_for(TINY)
+    om = torch.tensor(CO.omega_m, dtype=torch.float64, requires_grad=True)
+    s8 = torch.tensor(CO.sigma8, dtype=torch.float64, requires_grad=True)
+    n1 = dev(white_noise(8, 2)).requires_grad_(True)
+    n2 = dev(white_noise(8, 3)).requires_grad_(True)
+    d1 = api.simulate(pm, n1, om, s8)[2]
+    d2 = api.simulate(pm, n2, om, s8)[2]
+    with pytest.raises(RuntimeError, match="another forward"):
+        (d1.double() ** 2).mean().backward()
+    (d2.double() ** 2).mean().backward()        # the latest graph still works
+    assert torch.isfinite(n2.grad).all()
 
 
 # ---------------------------------------------------------------- filter
@@ -168,7 +194,7 @@ def test_zero_last_layer_reproduces_plain_pm_bitwise():
 def test_filter_gradients_match_oracle():
     w = TINY
     theta = 0.5 * mlp_init(0, zero_last=False)
-    noise, target, gdisp, gmom, ref = _grad_case(w, 3, 4, theta)
+    noise, target, gdisp, gmom, ref, _ = oracle_gradients(w, 3, 4, theta)
     pm = context(w.ptcl_grid, w.mesh, w.box, w.n_steps, filter=True)
     pm.set_filter(dev(theta))
     disp, mom, dens = pm.forward(dev(noise))
@@ -242,7 +268,7 @@ def test_filter_training_reduces_loss():
     from paper_2211_09958_amd import train_filter
     rep = train_filter.main(["--ptcl", "16", "--box", "16", "--steps", "8", "--train-seeds", "4",
                              "--heldout", "2", "--batch", "2", "--epochs", "24", "--lr", "1e-2",
-                             "--log-every", "8"])
+                             "--n-bins", "8", "--log-every", "8"])
     h = rep["history"]
     assert rep["adam_steps"] == 48
     total = [e["loss_pk"] + e["loss_disp"] for e in h]
