@@ -15,6 +15,7 @@
 // axis-0 pass: one load of the spectrum, one forward column FFT, then for each
 // j a multiply and inverse column FFT straight to the output buffer, so the
 // spectrum is read once and each gradient component written once.
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -250,6 +251,96 @@ k_grad_z(const float2* __restrict__ src, float2* __restrict__ dst, long dstStrid
     for (int e = 0; e < E; ++e) dst[off(j + e * T)] = lds[lpad(j + e * T) * W + c];
 }
 
+// k_grad_z for the largest transforms, whose register footprint allows one
+// work-group per CU: a persistent loop over tiles in which the column of the
+// next tile is loaded while the current one is transformed, so that the loads
+// overlap the transforms instead of alternating with them.  Work-group b takes
+// tiles lw, lw + nwg, ... with lw its XCD-contiguous index, so the work-groups
+// of one XCD work on neighbouring column blocks at any time.
+template <int H>
+__global__ void __launch_bounds__(Cfg<H>::T * Cfg<H>::W)
+k_grad_z_pipe(const float2* __restrict__ src, float2* __restrict__ dst, long dstStride, int cs,
+              int ncb, int ntiles, const float* __restrict__ radial, const float2* __restrict__ tw,
+              int ntw, const float2* __restrict__ st) {
+    constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::W, n = H;
+    constexpr int LS = lds_slots(H) * W;
+    static_assert(T % 16 == 0, "rows j + e T must share their in-block index");
+    // lds: the transforms' exchange buffer; keep: radial * delta_k of the
+    // column (held in LDS rather than registers, which hold the next column)
+    __shared__ float2 lds[2 * LS];
+    float2* keep = lds + LS;
+    const int c = threadIdx.x % W, j = threadIdx.x / W;
+    const int nwg = (int)gridDim.x;
+    const int lw = (int)xcd_block(blockIdx.x, gridDim.x);
+    // Element p = j + e T of the column of tile (i1, cb) sits at
+    //   mesh_row(p, i1) cs + cb W + c = e T n cs + [mesh_row(j, 0) + mesh_row(0, i1)] cs + cb W + c
+    // in the blocked order (block and in-block indices are sums of separate i0
+    // and i1 terms, and T is a multiple of the block side): a wave-uniform part
+    // e T n cs and a per-lane part below 2^32 bytes.
+    const long estride = (long)T * n * cs;
+    auto lane_off = [&](int tile) -> uint32_t {
+        return (uint32_t)(((mesh_row(j, 0, n) + mesh_row(0, tile / ncb, n)) * cs +
+                           (tile % ncb) * W + c) * sizeof(float2));
+    };
+    auto at = [](const float2* base, long e_off, uint32_t lane) -> const float2* {
+        return reinterpret_cast<const float2*>(reinterpret_cast<const char*>(base + e_off) + lane);
+    };
+    float2 nx[E];
+    if (lw < ntiles) {
+        const uint32_t lo = lane_off(lw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) nx[e] = *at(src, e * estride, lo);
+    }
+    for (int tile = lw; tile < ntiles; tile += nwg) {
+        const int i1 = tile / ncb, k2 = (tile % ncb) * W + c;
+        const uint32_t lo = lane_off(tile);
+        float2 v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = nx[e];
+        if (tile + nwg < ntiles) {
+            const uint32_t ln = lane_off(tile + nwg);
+#pragma unroll
+            for (int e = 0; e < E; ++e) nx[e] = *at(src, e * estride, ln);
+        }
+        fft_lds<H, E, -1>(v, lds, W, c, j, st);
+        __syncthreads();
+        const int n1 = signed_freq(i1, n);
+        const bool in_half = k2 <= n / 2;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = j + e * T;
+            const int n0 = signed_freq(p, n);
+            const float rad = in_half ? radial[n0 * n0 + n1 * n1 + k2 * k2] : 0.f;
+            const float2 x = lds[lpad(p) * W + c];
+            v[e] = make_float2(rad * x.x, rad * x.y);
+            keep[lpad(p) * W + c] = v[e];
+        }
+        __syncthreads();
+        fft_lds<H, E, 1>(v, lds, W, c, j, st);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            *const_cast<float2*>(at(dst + dstStride, e * estride, lo)) = lds[lpad(j + e * T) * W + c];
+        // F~_0 multiplier i n0 (zero on the Nyquist plane) on the kept column;
+        // each lane reads back only the slots it wrote itself
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = j + e * T;
+            const int n0 = signed_freq(p, n);
+            const float f0 = n0 == -n / 2 ? 0.f : (float)n0;
+            const float2 d = keep[lpad(p) * W + c];
+            v[e] = make_float2(-d.y * f0, d.x * f0);
+        }
+        __syncthreads();
+        fft_lds<H, E, 1>(v, lds, W, c, j, st);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            *const_cast<float2*>(at(dst, e * estride, lo)) = lds[lpad(j + e * T) * W + c];
+        __syncthreads();   // the next tile's first transform reuses lds
+    }
+}
+
 // Axis-0 pass of the transposed gradient operator (see launch_grad_adj_z).
 // Sum_j conj(i n_j R) G_j = -i R (n0 G_0 + n1 G_1 + n2 G_2); n1 and n2 are fixed
 // along the column, so n1 G_1 + n2 G_2 is combined before its forward FFT:
@@ -357,6 +448,16 @@ k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
     for (int e = 0; e < E; ++e) dst[off(j + e * T)] = lds[lpad(j + e * T) * W + c];
 }
 
+// Compute units of the current device (work-groups of the persistent passes).
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return 256;
+    return cus;
+}
+
 // Calls f(std::integral_constant<int, n>) for the supported power-of-two sizes.
 template <class F>
 void size_switch(int n, F&& f) {
@@ -448,8 +549,15 @@ void launch_grad_z(const float2* src, float2* dst, long dstStride, int n, int cs
         constexpr int NN = decltype(nn)::value;
         constexpr int W = Cfg<NN>::W, T = Cfg<NN>::T;
         int ncb = cs / W;
-        hipLaunchKernelGGL(k_grad_z<NN>, dim3(NN * ncb), dim3(T * W), 0, s, src, dst,
-                           dstStride, cs, ncb, radial, tw.w, tw.n, tw.stages);
+        if constexpr (NN == 1024) {
+            const int ntiles = NN * ncb;
+            const int nwg = std::min(ntiles, device_cus());
+            hipLaunchKernelGGL(k_grad_z_pipe<NN>, dim3(nwg), dim3(T * W), 0, s, src, dst,
+                               dstStride, cs, ncb, ntiles, radial, tw.w, tw.n, tw.stages);
+        } else {
+            hipLaunchKernelGGL(k_grad_z<NN>, dim3(NN * ncb), dim3(T * W), 0, s, src, dst,
+                               dstStride, cs, ncb, radial, tw.w, tw.n, tw.stages);
+        }
     });
 }
 
