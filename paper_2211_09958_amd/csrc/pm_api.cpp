@@ -158,8 +158,12 @@ struct Plan {
         losstab = take(ntab_f * sizeof(float));
         tw = take((size_t)ng * sizeof(float2));
         tw_stages = take(kStageTableSize * sizeof(float2));
-        // FP64 block partials: one per 256-particle block, three sets for the IC check
-        partials = take((3 * (size_t)((P + 255) / 256) + 3 * 4096) * sizeof(double));
+        // FP64 block partials: three sets of at most 4096 grid-stride blocks (IC
+        // check, dot products, losses), and one per tile for the tile-based
+        // gathers, whose count nt^3 exceeds that when the mesh has many more
+        // cells than there are particles (32768 tiles at 512^3)
+        partials = take(std::max(3 * (size_t)((P + 255) / 256) + 3 * 4096,
+                                 (size_t)nt * nt * nt) * sizeof(double));
         sums = take((2 * (size_t)c.n_steps + 2 + kExtraSlots) * sizeof(double));
         maxbits = take(kExtraSlots * sizeof(unsigned));
         pkbins = take(3 * (size_t)ng * sizeof(double));
