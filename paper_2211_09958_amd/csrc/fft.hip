@@ -458,6 +458,92 @@ int device_cus() {
     return cus;
 }
 
+// k_grad_adj_z (without the filter cotangent) for the largest transforms, as a
+// persistent loop like k_grad_z_pipe: the G_0 column of the next tile is loaded
+// during the current tile's transforms, the current tile's G_1 and G_2 columns
+// are loaded before its first transform, and the sum
+// n0 G_0 + n1 G_1 + n2 G_2 of the forward transforms is kept in LDS.
+template <int H>
+__global__ void __launch_bounds__(Cfg<H>::T * Cfg<H>::W)
+k_grad_adj_z_pipe(const float2* __restrict__ src, long srcStride, float2* dst, int cs, int ncb,
+                  int ntiles, const float* __restrict__ radial, const float2* __restrict__ tw,
+                  int ntw, const float2* __restrict__ st) {
+    constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::W, n = H;
+    constexpr int LS = lds_slots(H) * W;
+    static_assert(T % 16 == 0, "rows j + e T must share their in-block index");
+    __shared__ float2 lds[2 * LS];
+    __shared__ float2 twl[H];   // this length's stage twiddles
+    float2* keep = lds + LS;
+    const int c = threadIdx.x % W, j = threadIdx.x / W;
+    for (int i = threadIdx.x; i < H; i += T * W) twl[i] = st[H + i];
+    __syncthreads();
+    const int nwg = (int)gridDim.x;
+    const int lw = (int)xcd_block(blockIdx.x, gridDim.x);
+    // wave-uniform row-block part e T n cs and a 32-bit lane part (k_grad_z_pipe)
+    const long estride = (long)T * n * cs;
+    auto lane_off = [&](int tile) -> uint32_t {
+        return (uint32_t)(((mesh_row(j, 0, n) + mesh_row(0, tile / ncb, n)) * cs +
+                           (tile % ncb) * W + c) * sizeof(float2));
+    };
+    auto at = [](const float2* base, long e_off, uint32_t lane) -> const float2* {
+        return reinterpret_cast<const float2*>(reinterpret_cast<const char*>(base + e_off) + lane);
+    };
+    const float2* g1 = src + srcStride;
+    const float2* g2 = src + 2 * srcStride;
+    for (int tile = lw; tile < ntiles; tile += nwg) {
+        const int i1 = tile / ncb, k2 = (tile % ncb) * W + c;
+        const uint32_t lo = lane_off(tile);
+        const int n1 = signed_freq(i1, n);
+        const bool in_half = k2 <= n / 2;
+        const float f1 = n1 == -n / 2 ? 0.f : (float)n1;
+        const float f2 = k2 == n / 2 ? 0.f : (float)k2;
+        float2 v[E], y1[E], y2[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = *at(src, e * estride, lo);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            y1[e] = *at(g1, e * estride, lo);
+            y2[e] = *at(g2, e * estride, lo);
+        }
+        // forward FFT of G_0, kept as n0 G_0 (zero on its Nyquist plane)
+        fft_lds_tab<H, E, -1>(v, lds, W, c, j, twl);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = j + e * T;
+            const int n0 = signed_freq(p, n);
+            const float f0 = n0 == -n / 2 ? 0.f : (float)n0;
+            const float2 g = lds[lpad(p) * W + c];
+            keep[lpad(p) * W + c] = make_float2(f0 * g.x, f0 * g.y);
+        }
+        // forward FFT of n1 G_1 + n2 G_2, added to the kept column
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            v[e] = make_float2(f1 * y1[e].x + f2 * y2[e].x, f1 * y1[e].y + f2 * y2[e].y);
+        __syncthreads();
+        fft_lds_tab<H, E, -1>(v, lds, W, c, j, twl);
+        __syncthreads();
+        // delta_bar_k = -i R (n0 G_0 + n1 G_1 + n2 G_2); each lane reads back only
+        // the kept slots it wrote itself
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = j + e * T;
+            const int n0 = signed_freq(p, n);
+            const float rad = in_half ? radial[n0 * n0 + n1 * n1 + k2 * k2] : 0.f;
+            const float2 g = lds[lpad(p) * W + c], k = keep[lpad(p) * W + c];
+            const float2 a = make_float2(k.x + g.x, k.y + g.y);
+            v[e] = make_float2(rad * a.y, -rad * a.x);
+        }
+        __syncthreads();
+        fft_lds_tab<H, E, 1>(v, lds, W, c, j, twl);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            *const_cast<float2*>(at(dst, e * estride, lo)) = lds[lpad(j + e * T) * W + c];
+        __syncthreads();   // the next tile's first transform reuses lds
+    }
+}
+
 // Calls f(std::integral_constant<int, n>) for the supported power-of-two sizes.
 template <class F>
 void size_switch(int n, F&& f) {
@@ -568,14 +654,20 @@ void launch_grad_adj_z(const float2* src, long srcStride, float2* dst, const flo
         constexpr int NN = decltype(nn)::value;
         constexpr int W = Cfg<NN>::W, T = Cfg<NN>::T;
         int ncb = cs / W;
-        if (fbar)
+        if (fbar) {
             hipLaunchKernelGGL((k_grad_adj_z<NN, true>), dim3(NN * ncb), dim3(T * W), 0, s, src,
                                srcStride, dst, dens, cs, ncb, radial, fbar, fscale, tw.w, tw.n,
                                tw.stages);
-        else
+        } else if constexpr (NN == 1024) {
+            const int ntiles = NN * ncb;
+            const int nwg = std::min(ntiles, device_cus());
+            hipLaunchKernelGGL(k_grad_adj_z_pipe<NN>, dim3(nwg), dim3(T * W), 0, s, src,
+                               srcStride, dst, cs, ncb, ntiles, radial, tw.w, tw.n, tw.stages);
+        } else {
             hipLaunchKernelGGL((k_grad_adj_z<NN, false>), dim3(NN * ncb), dim3(T * W), 0, s, src,
                                srcStride, dst, dens, cs, ncb, radial, fbar, fscale, tw.w, tw.n,
                                tw.stages);
+        }
     });
 }
 

@@ -189,4 +189,15 @@ __device__ __forceinline__ void fft_lds(float2 (&v)[E], float2* lds, int PS, int
     fft_stage<H, E, DIR, 1>(v, lds, PS, off, j, stages + H);
 }
 
+// As fft_lds, with `tab` the H-point transform's own part of the stage table
+// (stages + H), e.g. a copy in LDS: loads from LDS are not hoisted across the
+// stage barriers, so the twiddles do not stay live in registers.
+template <int H, int E, int DIR>
+__device__ __forceinline__ void fft_lds_tab(float2 (&v)[E], float2* lds, int PS, int off, int j,
+                                            const float2* tab) {
+    static_assert((H & (H - 1)) == 0 && (E & (E - 1)) == 0 && E <= H, "power-of-two sizes");
+    static_assert(E == fft_values_per_lane(H), "lane shape must match the twiddle tables");
+    fft_stage<H, E, DIR, 1>(v, lds, PS, off, j, tab);
+}
+
 }  // namespace pmx
