@@ -269,6 +269,25 @@ int pm_loss_disp(pm_ctx* ctx, const float* disp_dev, const float* disp_target_de
 int pm_power_spectrum(pm_ctx* ctx, const float* dens_dev, int32_t n_bins,
                       double* k_host, double* pk_host, double* nmodes_host);
 
+/* pm_power_spectrum without a context or workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving or
+ * training loops, harnesses that forbid hipMalloc).  Same shells, estimator and
+ * outputs as pm_power_spectrum for an [mesh]^3 overdensity dens_dev in a box of
+ * side box (Mpc/h), 8 <= mesh <= PM_NOALLOC_MAX_MESH (power of two),
+ * 1 <= n_bins <= mesh.  Runs on the current device, on hip_stream (NULL = the
+ * default stream, which must belong to that device), and synchronises it.
+ * Allocates nothing: its scratch (the half spectrum, twiddle tables and shell
+ * sums) is a static device array of PM_NOALLOC_SCRATCH_BYTES that every GPU the
+ * library runs on holds until the process ends; the first call on a device sets
+ * it up.  All calls on one GPU share that array, so calls that overlap on one
+ * GPU (two streams or two host threads) race.  Errors: PM_EINVAL (arguments,
+ * checked before any GPU work), PM_EHIP; message via pm_last_error(NULL). */
+#define PM_NOALLOC_MAX_MESH 128
+#define PM_NOALLOC_SCRATCH_BYTES 10506240u
+int pm_power_spectrum_noalloc(const float* dens_dev, int32_t mesh, double box, int32_t n_bins,
+                              double* k_host, double* pk_host, double* nmodes_host,
+                              void* hip_stream);
+
 /* Building blocks of the step, on the context's geometry, for tests and tools.
  *   pm_density:   dens_dev = CIC overdensity of particles at q + disp
  *   pm_force:     force_dev [Np^3][3] = PM force at q + disp, filter (if on)

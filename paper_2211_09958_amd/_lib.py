@@ -19,13 +19,14 @@ PM_MAX_CHECKPOINTS = 64
 N_FILTER_PARAMS = 4417
 PM_F_TIMING = 1
 PM_F_2LPT = 2
+PM_NOALLOC_MAX_MESH = 128
 KERNEL_FAMILIES = ("bin", "scatter", "scatter_vec", "fft_x", "fft_strided", "grad_z",
                    "grad_adj_z", "gather", "unkick_vjp", "wgrad", "mlp", "other")
 
 # exported entry points, in the order include/pm.h declares them
 EXPORTS = ("pm_workspace_bytes", "pm_host_tables", "pm_state_units", "pm_init",
            "pm_set_cosmology", "pm_set_filter", "pm_forward", "pm_adjoint", "pm_loss_mse", "pm_loss_pk",
-           "pm_loss_disp", "pm_power_spectrum",
+           "pm_loss_disp", "pm_power_spectrum", "pm_power_spectrum_noalloc",
            "pm_density", "pm_force", "pm_force_vjp", "pm_fft_r2c", "pm_fft_c2r",
            "pm_lpt2_growth", "pm_initial_conditions", "pm_set_step_scales",
            "pm_step_gradients",
@@ -88,6 +89,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "pm_loss_pk": (c_int, [P, P, c_int32, P, c_double, P, P]),
         "pm_loss_disp": (c_int, [P, P, P, c_double, P, P]),
         "pm_power_spectrum": (c_int, [P, P, c_int32, P, P, P]),
+        "pm_power_spectrum_noalloc": (c_int, [P, c_int32, c_double, c_int32, P, P, P, P]),
         "pm_density": (c_int, [P, P, P]),
         "pm_force": (c_int, [P, P, c_double, P]),
         "pm_force_vjp": (c_int, [P, P, c_double, P, P]),

@@ -87,6 +87,24 @@ def lpt2_growth(cfg: Config, cosmo):
     return {"D2": out[0], "G2": out[1], "d_D2": out[2], "d_G2": out[3]}
 
 
+def power_spectrum_noalloc(dens, box, n_bins=None, stream=None):
+    """pm_power_spectrum_noalloc: P(k) of an [Ng]^3 float32 overdensity on the
+    current device without a context (no device allocation by the library;
+    Ng <= PM_NOALLOC_MAX_MESH).  Returns (k, P, modes) as host arrays."""
+    import numpy as np
+    if dens.dtype != torch.float32 or not dens.is_contiguous() or dens.dim() != 3:
+        raise ValueError("dens must be a contiguous [Ng]^3 float32 tensor")
+    ng = dens.shape[0]
+    n_bins = ng // 2 if n_bins is None else n_bins
+    k, pk, nm = np.zeros(n_bins), np.zeros(n_bins), np.zeros(n_bins)
+    s = torch.cuda.current_stream(dens.device) if stream is None else stream
+    p = lambda a: a.ctypes.data_as(c_void_p)
+    with torch.cuda.device(dens.device):
+        check(_lib.load().pm_power_spectrum_noalloc(_ptr(dens), ng, float(box), n_bins, p(k),
+                                                    p(pk), p(nm), c_void_p(s.cuda_stream)))
+    return k, pk, nm
+
+
 class PMContext:
     """One simulation geometry on one GPU (a pm_ctx plus its torch workspace)."""
 

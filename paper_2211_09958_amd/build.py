@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpmx.so")
 
-HIP_SOURCES = ["fft.hip", "particles.hip", "mlp.hip"]
+HIP_SOURCES = ["fft.hip", "particles.hip", "mlp.hip", "noalloc.hip"]
 HOST_SOURCES = ["pm_api.cpp", "host_cosmo.cpp"]
 
 ARCH = os.environ.get("PMX_OFFLOAD_ARCH", "gfx950")

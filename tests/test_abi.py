@@ -65,6 +65,17 @@ def test_pm_init_validates_before_touching_the_gpu():
     assert lib.pm_adjoint(None, None, None, None, None, None, None) == _lib.PM_EINVAL
 
 
+def test_noalloc_power_spectrum_validates_before_touching_the_gpu():
+    lib = _lib.load()
+    k = (ctypes.c_double * 8)()
+    fake = ctypes.c_void_p(256)   # never dereferenced: every case fails validation
+    for mesh, box, nb, dens in ((12, 12.0, 4, fake), (256, 256.0, 8, fake), (64, -1.0, 8, fake),
+                                (64, 64.0, 0, fake), (64, 64.0, 65, fake), (64, 64.0, 8, None)):
+        rc = lib.pm_power_spectrum_noalloc(dens, mesh, box, nb, k, k, k, None)
+        assert rc == _lib.PM_EINVAL, (mesh, box, nb)
+        assert lib.pm_last_error(None)
+
+
 def test_workspace_scales_with_mesh_not_steps():
     a = api.workspace_bytes(api.config_from_workload(MEDIUM))
     b = api.workspace_bytes(api.config_from_workload(MEDIUM.with_(n_steps=630)))
