@@ -17,10 +17,10 @@ and stores what the GPU tests compare against:
       final displacement at seeded sample indices, and the final P(k).
   filter_32p_512m_2steps.json
       32^3 particles, 512^3 mesh, box 512, two steps a = 1/64 -> 3/64, learned
-      filter with weights 0.5 * mlp_init(0, zero_last=False): the full noise
-      and filter gradients, the Omega_m and sigma_8 gradients and the final
-      displacements (MSE loss against seed 32 plus a seeded displacement
-      cotangent).  Few heavy particles make trajectories sensitive to rounding:
+      filter with weights 0.5 * mlp_init(0, zero_last=False): the 4417 filter
+      gradients, the Omega_m and sigma_8 gradients, the noise gradient (norm and
+      4096 sampled sites) and 2048 sampled final displacements (MSE loss against
+      seed 32 plus a seeded displacement cotangent).  Few heavy particles make trajectories sensitive to rounding:
       with 16^3 particles (32^3 cells each) the oracle's own filter gradient moves
       by 12 % under a 1e-6 relative perturbation of the noise even in these two
       early steps; with 32^3 particles (16^3 cells each, as 16^3 particles on the
@@ -130,6 +130,8 @@ def filter_case():
     gdisp = normal((np_ ** 3, 3), 33) * 1e-3
     ref = opm.adjoint(run, noise, g_dens=gd, g_disp=gdisp)
     print(f"filter case {time.time() - t0:.0f} s", flush=True)
+    gi = sample_indices(np_ ** 3, 4096, 9)
+    pi = sample_indices(np_ ** 3, 2048, 10)
     out = {
         "config": {"ptcl_grid": np_, "mesh": ng, "box": box, "n_steps": steps,
                    "a_start": st.a_start, "a_stop": st.a_stop, "seed": 31, "target_seed": 32,
@@ -137,9 +139,12 @@ def filter_case():
                    "g_disp": "1e-3 * normal((32**3, 3), 33)", "cosmology": CO.__dict__},
         "loss": loss,
         "g_omega_m": ref.omega_m, "g_sigma8": ref.sigma8,
-        "g_noise": ref.noise.reshape(-1).tolist(),
         "g_theta": ref.theta.tolist(),
-        "disp": run.disp[-1].tolist(),
+        "g_noise_norm": float(np.linalg.norm(ref.noise)),
+        "g_noise_index": gi.tolist(),
+        "g_noise_sample": ref.noise.reshape(-1)[gi].tolist(),
+        "disp_index": pi.tolist(),
+        "disp_sample": run.disp[-1][pi].tolist(),
     }
     with open(FILTER_FILE, "w") as f:
         json.dump(out, f)
