@@ -64,6 +64,11 @@ def parse():
     return p.parse_args()
 
 
+def progress(msg):
+    """One line per finished piece of work, on stderr (stdout carries the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def cpu_baseline():
     """The FP64 oracle, as it stands, on a bounded sample of the workload: 64^3
     particles on a 128^3 mesh in a 64 Mpc/h box (the headline's cell size and
@@ -144,8 +149,9 @@ def main():
         last["disp"] = disp
         return g_cosmo
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         step(pm)
+        progress(f"warm-up run {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     pm.reset_stats()
     if args.calib_copy_gib > 0:
@@ -161,8 +167,9 @@ def main():
     marker.fill_(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        g_cosmo = step(pm)
+    for i in range(args.steps):
+        g_cosmo = step(pm)   # returns host values: the stream has synchronised
+        progress(f"timed run {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     marker.fill_(2)
@@ -230,20 +237,25 @@ def main():
         out["pure_reverse"] = {"value": P * w.n_steps / dtp, "ms_per_step": dtp * 1e3,
                                "ic_rms_cells": sp["ic_rms_cells"],
                                "ic_max_cells": sp["ic_max_cells"]}
+        progress("pure reverse-time variant done")
     if not args.no_medium and w.name == "pm-512p-1024m-63s":
         pm = pure = None
         torch.cuda.empty_cache()
         out["medium"] = medium_leg(args, co)
+        progress("256^3/512^3 leg done")
     if not args.no_lpt2:
         pm = pure = None
         torch.cuda.empty_cache()
         out["lpt2"] = lpt2_leg(args, w, co, noise, target, fams, make)
+        progress("2LPT leg done")
     if not args.no_learned and os.path.exists(args.weights) and w.name == "pm-512p-1024m-63s":
         pm = pure = None   # release the 1024^3 workspaces
         torch.cuda.empty_cache()
         out["learned_vs_plain"] = learned_vs_plain(args, co, noise, last["disp"], value)
+        progress("learned-filter leg done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
+        progress("CPU baseline done")
     print(json.dumps(out))
 
 

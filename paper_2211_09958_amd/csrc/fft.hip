@@ -27,6 +27,14 @@
 namespace pmx {
 namespace {
 
+// Non-temporal store of one complex value (the last-axis passes write data that
+// no later pass reads before the whole buffer has streamed through the caches;
+// measured 3 % faster there, 7 % slower in the strided passes).
+__device__ __forceinline__ void st_nt(float2* p, float2 v) {
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+}
+
 // Lanes-per-transform and values-per-lane choices per transform length.
 template <int H>
 struct Cfg {
@@ -74,9 +82,9 @@ k_fft_x_r2c(float2* __restrict__ buf, int cs, long nrows, long bufStride,
         float2 X = make_float2(0.5f * (A.x - iwB.x), 0.5f * (A.y - iwB.y));
         if (k == 0) {
             X = make_float2(zk.x + zk.y, 0.f);
-            rowp[H] = make_float2(zk.x - zk.y, 0.f);
+            st_nt(&rowp[H], make_float2(zk.x - zk.y, 0.f));
         }
-        rowp[k] = X;
+        st_nt(&rowp[k], X);
     }
 }
 
@@ -120,7 +128,7 @@ k_fft_x_c2r(float2* __restrict__ buf, int cs, long nrows, long bufStride, int km
     __syncthreads();
     if (!valid) return;
 #pragma unroll
-    for (int e = 0; e < E; ++e) rowp[j + e * T] = L[lpad(j + e * T)];
+    for (int e = 0; e < E; ++e) st_nt(&rowp[j + e * T], L[lpad(j + e * T)]);
 }
 
 // ---------------------------------------------------------- strided axes
@@ -448,16 +456,6 @@ k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
     for (int e = 0; e < E; ++e) dst[off(j + e * T)] = lds[lpad(j + e * T) * W + c];
 }
 
-// Compute units of the current device (work-groups of the persistent passes).
-int device_cus() {
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0)
-        return 256;
-    return cus;
-}
-
 // k_grad_adj_z (without the filter cotangent) for the largest transforms, as a
 // persistent loop like k_grad_z_pipe: the G_0 column of the next tile is loaded
 // during the current tile's transforms, the current tile's G_1 and G_2 columns
@@ -669,6 +667,15 @@ void launch_grad_adj_z(const float2* src, long srcStride, float2* dst, const flo
                                tw.stages);
         }
     });
+}
+
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return 256;
+    return cus;
 }
 
 void fill_stage_twiddles(float2* table) {

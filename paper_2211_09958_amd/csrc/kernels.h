@@ -23,6 +23,8 @@ struct Twiddles {
 };
 // Host: fill the per-stage twiddle table (kStageTableSize entries).
 void fill_stage_twiddles(float2* table);
+// Compute units of the current device (work-groups of the persistent kernels).
+int device_cus();
 
 // ---------------------------------------------------------------- FFT
 // Real rows -> half spectra along the last axis, in place, for `nbuf` buffers

@@ -316,6 +316,21 @@ def test_field_level_reconstruction_recovers_the_noise(lpt):
     assert r[: 3 * len(r) // 4].min() > 0.95, r
 
 
+def test_field_level_reconstruction_in_a_nonlinear_box():
+    """The same fit where the final field is nonlinear (64^3 particles, 128^3
+    mesh, box 128 Mpc/h: 2 Mpc/h spacing, 15 steps to a = 1).  Adam's step must
+    be small there (lr 0.02 stalls, 0.05 diverges); with lr 0.01 and 300 steps
+    the loss drops below half and the recovered noise correlates with the truth
+    at r > 0.75 in the four largest-scale shells."""
+    from paper_2211_09958_amd import reconstruct
+    rep = reconstruct.main(["--ptcl", "64", "--mesh", "128", "--box", "128", "--steps", "15",
+                            "--iters", "300", "--lr", "0.01", "--log-every", "100"])
+    r = np.array(rep["noise_cross_correlation"])
+    print(f"loss {rep['loss_first']:.3e} -> {rep['loss_last']:.3e}; r(k) {np.round(r[:8], 3)}")
+    assert rep["loss_last"] < 0.5 * rep["loss_first"]
+    assert r[:4].min() > 0.75, r[:4]
+
+
 # ------------------------------------------------------- failure handling, resume
 
 def test_nonfinite_cotangent_reports_enumeric_and_context_recovers():
