@@ -124,9 +124,11 @@ void launch_scatter_vec(const uint32_t* xq, const float* v, float coeff, unsigne
                         const Lattice& L, const Bins& b, float* out, long outStride,
                         hipStream_t s);
 
-// Gathers: one work-group per tile of the current bins (particles must be
-// sorted by those bins); partials (nullable) get one FP64 value per tile.
-long gather_blocks(const Bins& b);
+// Gathers: persistent work-groups over the tiles of the current bins (particles
+// must be sorted by those bins); partials (nullable) get one FP64 value per
+// work-group: unkick_vjp_partials(b) and wgrad_partials(b) values.
+long unkick_vjp_partials(const Bins& b);
+long wgrad_partials(const Bins& b);
 // F = gather(force meshes), p += kick F, optional checkpoint copy of (x, p) in
 // lattice order (by id), then x += drift p (if do_drift).  *ovf (nullable) is
 // set to 1 when a new momentum does not fit the int32 fixed-point range.

@@ -309,12 +309,77 @@ __device__ __forceinline__ void tile_range(int r, int tx, int ty, int tz, int nt
 
 constexpr int kRanges = 20;
 
+// 64-bit fixed-point value of q (0 <= q < 2^62), rounded to nearest even: the
+// same integer as rounding the exact (double) q, from single-precision
+// operations only.  hi = floor(q / 2^32) is exact, and so is r = q - hi 2^32 in
+// [0, 2^32): below 2^32 it is q itself, above it is a multiple of q's last place
+// and at most 2^23 of those fit below 2^32; rounding r then rounds q.
+__device__ __forceinline__ unsigned long long to_fixed64_nonneg(float q) {
+    const float hi = floorf(q * 0x1p-32f);
+    const float r = __builtin_rintf(__fmaf_rn(hi, -0x1p32f, q));
+    return ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)r;
+}
+
+// The same for |q| < 2^62 of either sign (two's complement); rounding to
+// nearest even commutes with the sign.
+__device__ __forceinline__ unsigned long long to_fixed64(float q) {
+    const unsigned long long u = to_fixed64_nonneg(fabsf(q));
+    return q < 0.f ? 0ull - u : u;
+}
+
+// The 8 CIC corners of a particle at x that fall in the tile at lo, added to the
+// tile's accumulator as the fixed-point value of w val 2^e, w the corner's
+// weight (SIGNED: val may be negative).  Node
+// indices and weights are formed once per axis; a corner outside the tile
+// (the far node of a particle on the tile's last layer) is skipped.
+template <int T, bool SIGNED>
+__device__ __forceinline__ void deposit(unsigned long long* acc, const uint32_t x[3], float val,
+                                        int e, const Lattice& L, const int lo[3]) {
+    const int mask = L.ng - 1;
+    int ii[3];
+    float t[3];
+    locate(x, L, ii, t);
+    int l[3][2];
+    bool in[3][2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            int v = ((ii[a] + c) & mask) - lo[a];
+            if (v < 0) v += L.ng;
+            l[a][c] = v;
+            in[a][c] = v < T;
+        }
+    }
+#pragma unroll
+    for (int c0 = 0; c0 < 2; ++c0) {
+        if (!in[0][c0]) continue;
+        const float w0 = c0 ? t[0] : 1.f - t[0];
+#pragma unroll
+        for (int c1 = 0; c1 < 2; ++c1) {
+            if (!in[1][c1]) continue;
+            const float w01 = w0 * (c1 ? t[1] : 1.f - t[1]);
+            const int row = (l[0][c0] * T + l[1][c1]) * T;
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2) {
+                if (!in[2][c2]) continue;
+                const float w = w01 * (c2 ? t[2] : 1.f - t[2]);
+                const float q = ldexpf(w * val, e);
+                atomicAdd(&acc[row + l[2][c2]], SIGNED ? to_fixed64(q) : to_fixed64_nonneg(q));
+            }
+        }
+    }
+}
+
 // One work-group per tile.  Densities accumulate mass * w in 64-bit fixed
 // point with 2^32 units; the vector scatter (VEC) accumulates coeff * v_j * w
 // one component at a time, in 64-bit fixed point whose unit is chosen from
 // max |coeff * v| and the particle count so that no sum can overflow.  Integer
 // LDS atomics are both order-independent (bitwise reproducible results) and far
-// faster on gfx950 than floating-point LDS atomics.
+// faster on gfx950 than floating-point LDS atomics.  The kernel is bound by its
+// vector-ALU instruction count (a wave64 instruction takes four cycles), so the
+// per-corner work is kept to an index add, two products and the fixed-point
+// conversion, and the write-out handles four cells per thread.
 // Threads per scatter work-group; the 32 KB accumulator tile leaves room for
 // four work-groups per CU, so larger ones keep more waves in flight.
 constexpr int scatter_threads() { return 2 * kBlock; }
@@ -324,44 +389,49 @@ __global__ void __launch_bounds__(scatter_threads())
 k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, float coeff,
                const unsigned* __restrict__ vmax_bits, Lattice L, int nt,
                const uint32_t* __restrict__ offsets, float* __restrict__ out, long outStride) {
-    constexpr int T3 = T * T * T;
-    __shared__ unsigned long long acc[T3];
+    constexpr int T3 = T * T * T, NTH = scatter_threads();
+    static_assert(T % 4 == 0, "the write-out handles four cells of a row at a time");
+    __shared__ __align__(16) unsigned long long acc[T3];
     __shared__ uint32_t rs[kRanges], pre[kRanges + 1];
     const uint32_t tile = xcd_block(blockIdx.x, gridDim.x);
     const int tx = compact3(tile >> 2), ty = compact3(tile >> 1), tz = compact3(tile);
     const int lo[3] = {tx * T, ty * T, tz * T};
-    if (threadIdx.x < kRanges) {
-        uint32_t b, e;
-        tile_range(threadIdx.x, tx, ty, tz, nt, offsets, &b, &e);
-        rs[threadIdx.x] = b;
-        pre[threadIdx.x + 1] = e - b;
+    if (threadIdx.x < 64) {   // ranges and their prefix sum, in the first wave
+        const int lane = threadIdx.x;
+        uint32_t b = 0, e = 0;
+        if (lane < kRanges) tile_range(lane, tx, ty, tz, nt, offsets, &b, &e);
+        uint32_t incl = lane < kRanges ? e - b : 0u;
+        for (int o = 1; o < 32; o <<= 1) {   // kRanges <= 32 lanes take part
+            const uint32_t y = (uint32_t)__shfl_up((int)incl, o);
+            if (lane >= o) incl += y;
+        }
+        if (lane < kRanges) {
+            rs[lane] = b;
+            pre[lane + 1] = incl;
+        }
+        if (lane == 0) pre[0] = 0u;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        pre[0] = 0;
-        for (int r = 0; r < kRanges; ++r) pre[r + 1] += pre[r];
-    }
-    __syncthreads();
-    const int mask = L.ng - 1;
-    double scale = kFix, inv_scale = 1.0 / kFix;
+    int e = 32;
+    double inv_scale = 1.0 / kFix;
     float amp = (float)(L.ratio * L.ratio * L.ratio);   // mass
     if constexpr (VEC) {
         // |Sum| <= P max|coeff v|: unit 2^-e with 2^e <= 2^62 / (P max|coeff v|)
         const double vmax = (double)fabsf(coeff) * (double)__uint_as_float(*vmax_bits);
         const double P = (double)L.np * L.np * L.np;
-        int e = 0;
+        e = 0;
         if (vmax > 0.0) {
             frexp(P * vmax, &e);
             e = 61 - e;
         }
-        scale = ldexp(1.0, e);
         inv_scale = ldexp(1.0, -e);
         amp = coeff;
     }
     const uint32_t total = pre[kRanges];
     constexpr int NC = VEC ? 3 : 1;
+    ulonglong2* acc2 = reinterpret_cast<ulonglong2*>(acc);
     for (int comp = 0; comp < NC; ++comp) {
-        for (int c = threadIdx.x; c < T3; c += scatter_threads()) acc[c] = 0ull;
+        for (int c = threadIdx.x; c < T3 / 2; c += NTH) acc2[c] = make_ulonglong2(0ull, 0ull);
         __syncthreads();
         // one flat index space over the 20 ranges, so every lane has work; the
         // next particle's record is loaded before this one's atomics are issued
@@ -376,46 +446,27 @@ k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, 
             if (VEC) nv = vals[3 * p + comp];
         };
         if (threadIdx.x < total) fetch(threadIdx.x);
-        for (uint32_t k = threadIdx.x; k < total; k += scatter_threads()) {
+        for (uint32_t k = threadIdx.x; k < total; k += NTH) {
             const uint32_t cur[3] = {nx[0], nx[1], nx[2]};
             const float cv = nv;
-            if (k + scatter_threads() < total) fetch(k + scatter_threads());
-            int ii[3];
-            float t[3];
-            locate(cur, L, ii, t);
-            const float val = VEC ? amp * cv : amp;
-#pragma unroll
-            for (int c0 = 0; c0 < 2; ++c0) {
-                int l0 = ((ii[0] + c0) & mask) - lo[0];
-                if (l0 < 0) l0 += L.ng;
-                if (l0 >= T) continue;
-                const float w0 = c0 ? t[0] : 1.f - t[0];
-#pragma unroll
-                for (int c1 = 0; c1 < 2; ++c1) {
-                    int l1 = ((ii[1] + c1) & mask) - lo[1];
-                    if (l1 < 0) l1 += L.ng;
-                    if (l1 >= T) continue;
-                    const float w01 = w0 * (c1 ? t[1] : 1.f - t[1]);
-#pragma unroll
-                    for (int c2 = 0; c2 < 2; ++c2) {
-                        int l2 = ((ii[2] + c2) & mask) - lo[2];
-                        if (l2 < 0) l2 += L.ng;
-                        if (l2 >= T) continue;
-                        const float w = w01 * (c2 ? t[2] : 1.f - t[2]);
-                        const int cell = (l0 * T + l1) * T + l2;
-                        const double q = (double)(w * val) * scale;
-                        atomicAdd(&acc[cell], (unsigned long long)__double2ll_rn(q));
-                    }
-                }
-            }
+            if (k + NTH < total) fetch(k + NTH);
+            deposit<T, VEC>(acc, cur, VEC ? amp * cv : amp, e, L, lo);   // densities are >= 0
         }
         __syncthreads();
         float* o = out + comp * outStride;
-        for (int c = threadIdx.x; c < T3; c += scatter_threads()) {
+        for (int q = threadIdx.x; q < T3 / 4; q += NTH) {
+            const int c = 4 * q;
             const int l2 = c % T, l1 = (c / T) % T, l0 = c / (T * T);
             const long g = mesh_row(lo[0] + l0, lo[1] + l1, L.ng) * L.rp + lo[2] + l2;
-            const double v = (double)(long long)acc[c] * inv_scale;
-            o[g] = VEC ? (float)v : (float)(v - 1.0);
+            const ulonglong2 a = acc2[2 * q], b = acc2[2 * q + 1];
+            const unsigned long long v4[4] = {a.x, a.y, b.x, b.y};
+            float r4[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const double v = (double)(long long)v4[i] * inv_scale;
+                r4[i] = VEC ? (float)v : (float)(v - 1.0);
+            }
+            *reinterpret_cast<float4*>(o + g) = make_float4(r4[0], r4[1], r4[2], r4[3]);
         }
         __syncthreads();
     }
@@ -1148,7 +1199,8 @@ static void gather_dispatch(const GatherArgs& A, const Lattice& L, const Bins& b
     }
 }
 
-long gather_blocks(const Bins& b) { return (long)b.nt * b.nt * b.nt; }
+long unkick_vjp_partials(const Bins& b) { return (long)b.nt * b.nt * b.nt; }
+long wgrad_partials(const Bins& b) { return (long)b.nt * b.nt * b.nt; }
 
 void launch_gather_kick_drift(uint32_t* xq, int32_t* pq, const uint32_t* id, const float* fmesh,
                               long fStride, const Lattice& L, const Bins& b, float kick,

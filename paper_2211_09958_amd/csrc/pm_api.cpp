@@ -943,7 +943,7 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
     if (g_disp) PM_TRY(copy_d2d(ctx, ctx->xi, g_disp, vec));
     else launch_zero(ctx->xi, vec, s);
     compute_force(ctx, sc.a[N], true);
-    const int nbt = (int)gather_blocks(ctx->bins);
+    const int nbu = (int)unkick_vjp_partials(ctx->bins), nbw = (int)wgrad_partials(ctx->bins);
     if (g_dens) {
         KTimer t(ctx, PM_K_WGRAD, 24.0 * P + mesh_r(ctx->ng));
         launch_wgrad(g_dens, ctx->ng, mass, ctx->xq, ctx->pq, ctx->xi, ctx->pi, ctx->lat,
@@ -954,7 +954,7 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
         launch_unkick_vjp(ctx->xq, ctx->pq, ctx->creal(1), ctx->creal_stride(), ctx->lat,
                           ctx->bins, (float)sc.kick_b[N - 1], ctx->pi, ctx->xi, ctx->partials, s);
     }
-    launch_reduce(ctx->partials, nbt, ctx->sums, slotS + N, s);
+    launch_reduce(ctx->partials, nbu, ctx->sums, slotS + N, s);
 
     int nck = 0;
     for (int n = N - 1; n >= 0; --n) {
@@ -966,7 +966,7 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
             launch_wgrad(ctx->creal(0), ctx->lat.rp, mass, ctx->xq, ctx->pq, ctx->xi, ctx->pi,
                          ctx->lat, ctx->bins, (float)sc.drift[n], 1, ctx->partials, s);
         }
-        launch_reduce(ctx->partials, nbt, ctx->sums, slotD + n, s);
+        launch_reduce(ctx->partials, nbw, ctx->sums, slotD + n, s);
         // checkpoint: compare the reconstructed (x_n, p_{n+1/2}) and reset to it
         if (c.checkpoint_every > 0 && n > 0 && n % c.checkpoint_every == 0) {
             const int slot = n / c.checkpoint_every - 1;
@@ -992,7 +992,7 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
             launch_unkick_vjp(ctx->xq, ctx->pq, ctx->creal(1), ctx->creal_stride(), ctx->lat,
                               ctx->bins, (float)c0, ctx->pi, ctx->xi, ctx->partials, s);
         }
-        launch_reduce(ctx->partials, nbt, ctx->sums, slotS + n, s);
+        launch_reduce(ctx->partials, nbu, ctx->sums, slotS + n, s);
     }
     // (ii) + (iii) at x_0
     vjp_mesh(ctx, ctx->xq, ctx->pi, (float)sc.kick_a[0], sc.a[0]);

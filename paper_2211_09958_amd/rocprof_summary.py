@@ -82,9 +82,9 @@ def family(sym: str, ng: int):
         return "fft_strided", "2c_per_buf"
     if base == "k_fft_y_split" and targs[:1] == [str(ng)]:
         return "fft_strided", "3c"
-    if base == "k_grad_z" and targs[:1] == [str(ng)]:
+    if base in ("k_grad_z", "k_grad_z_pipe") and targs[:1] == [str(ng)]:
         return "grad_z", "3c"
-    if base == "k_grad_adj_z" and targs[:1] == [str(ng)]:
+    if base in ("k_grad_adj_z", "k_grad_adj_z_pipe") and targs[:1] == [str(ng)]:
         return "grad_adj_z", "5c" if targs[1:] == ["true"] else "4c"
     if base == "k_scatter_tile":
         return ("scatter_vec", "24P+3r") if targs[1:] == ["true"] else ("scatter", "12P+r")
@@ -121,6 +121,37 @@ def dispatches(db: str, counter: str | None = None):
             "where e.counter_name = ? order by k.dispatch_id", (counter,)).fetchall()
     con.close()
     return rows
+
+
+RESOURCE_COLUMNS = (("VGPRs", ("arch_vgpr_count", "vgpr_count")),
+                    ("AGPRs", ("accum_vgpr_count", "agpr_count")),
+                    ("SGPRs", ("sgpr_count",)),
+                    ("LDS bytes", ("group_segment_size", "lds_size", "lds_block_size")),
+                    ("scratch bytes", ("private_segment_size", "scratch_size")),
+                    ("work-group", ("workgroup_size",)))
+
+
+def resources(db: str):
+    """{kernel name: [(column label, value)]} from the per-dispatch resource columns
+    that the kernel trace records (register counts, LDS and scratch per work-group);
+    the column names differ between rocprofv3 versions, so they are looked up."""
+    con = sqlite3.connect(db)
+    cols = [r[1] for r in con.execute("pragma table_info(kernels)").fetchall()]
+    picked = []
+    for label, names in RESOURCE_COLUMNS:
+        for n in names:
+            if n in cols:
+                picked.append((label, n))
+                break
+    if "workgroup_size" not in cols and {"workgroup_x", "workgroup_y", "workgroup_z"} <= set(cols):
+        picked.append(("work-group", "workgroup_x * workgroup_y * workgroup_z"))
+    out = {}
+    if picked:
+        q = "select name, " + ", ".join(c for _, c in picked) + " from kernels group by name"
+        for row in con.execute(q).fetchall():
+            out[row[0]] = [(label, v) for (label, _), v in zip(picked, row[1:])]
+    con.close()
+    return out
 
 
 def timed_window(rows):
@@ -188,6 +219,16 @@ def main():
         if t / total < 1e-4:
             continue
         lines.append(f"| `{s}` | {n} | {t / 1e6:.2f} | {t / n / 1e6:.4f} | {100 * t / total:.2f} |")
+    res = {short(k): v for k, v in resources(a.kt).items()}
+    shown = [s for s, (n, t) in sorted(per_sym.items(), key=lambda kv: -kv[1][1])
+             if t / total >= 1e-4 and s in res]
+    if shown:
+        labels = [label for label, _ in res[shown[0]]]
+        lines += ["", "## Per kernel symbol: resources (from the kernel trace)", "",
+                  "| kernel | " + " | ".join(labels) + " |",
+                  "|---|" + "---|" * len(labels)]
+        for s in shown:
+            lines.append(f"| `{s}` | " + " | ".join(str(v) for _, v in res[s]) + " |")
     tag = a.workload
     with open(os.path.join(a.out, f"kernel-trace_all-kernels_{tag}.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
