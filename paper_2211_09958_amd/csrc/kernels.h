@@ -89,6 +89,7 @@ struct Bins {
     uint32_t* offsets;  // [nt^3 * 8 + 1]
     uint32_t* keys;     // [P]
     uint32_t* ranks;    // [P]
+    uint32_t* ord;      // [P] storage slot of the k-th particle in bin order
     uint32_t* scan_tmp; // scan block sums
     long nkeys() const { return (long)nt * nt * nt * 8; }
 };
@@ -111,9 +112,13 @@ struct Records {
 };
 
 // Counting sort of particles by (tile of the CIC base cell, spill class): bin
-// offsets into b, and every record array copied from src to dst in sorted
-// order (bins are contiguous ranges of the sorted arrays).
-void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, const Records& rec, hipStream_t s);
+// offsets and the sorted order b.ord (bin k of the offsets holds the particles
+// in storage slots ord[offsets[k]], ..., ord[offsets[k + 1] - 1]); the records
+// stay where they are.
+void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, hipStream_t s);
+// Moves every record array from src to dst in the order b.ord and resets b.ord
+// to the identity (each bin then a contiguous range of the records).
+void launch_compact(Bins& b, const Records& rec, long P, hipStream_t s);
 // Density delta = rho - 1 (particle mass (ng/np)^3) into a real mesh with pitch
 // L.rp; every cell written once (no pre-zeroing), deterministic.
 void launch_scatter_density(const uint32_t* xq, const Lattice& L, const Bins& b, float* mesh,
@@ -124,9 +129,10 @@ void launch_scatter_vec(const uint32_t* xq, const float* v, float coeff, unsigne
                         const Lattice& L, const Bins& b, float* out, long outStride,
                         hipStream_t s);
 
-// Gathers: persistent work-groups over the tiles of the current bins (particles
-// must be sorted by those bins); partials (nullable) get one FP64 value per
-// work-group: unkick_vjp_partials(b) and wgrad_partials(b) values.
+// Gathers: one work-group per tile of the current bins (the particles' state
+// is read and written in their storage slots, through b.ord); partials
+// (nullable) get one FP64 value per tile: unkick_vjp_partials(b) and
+// wgrad_partials(b) values.
 long unkick_vjp_partials(const Bins& b);
 long wgrad_partials(const Bins& b);
 // F = gather(force meshes), p += kick F, optional checkpoint copy of (x, p) in

@@ -19,9 +19,14 @@
 // Bins: particles are counting-sorted by the T^3-cell tile holding their base
 // node and by a 3-bit "spill class" (bit a set when the base node is on the
 // last layer of the tile along axis a, i.e. the CIC footprint reaches the next
-// tile).  A work-group owns one tile: it accumulates its own particles and the
-// spill classes of its 7 lower neighbours in LDS, then writes every cell of the
-// tile exactly once -- no atomics to HBM, no pre-zeroing, coalesced rows.
+// tile).  The sort produces an order, ord[k] = storage slot of the k-th
+// particle in bin order, rather than moving the records: particles move by a
+// fraction of a cell per step, so the slots of one bin stay in a few long
+// contiguous runs, and the records only need moving (compaction into bin
+// order) every few sorts.  A work-group owns one tile: it accumulates its own
+// particles and the spill classes of its 7 lower neighbours in LDS, then
+// writes every cell of the tile exactly once -- no atomics to HBM, no
+// pre-zeroing, coalesced rows.
 // Densities accumulate as 64-bit fixed point (2^-32 units), so the result does
 // not depend on the order of the LDS atomics (bitwise reproducible).
 #include <hip/hip_runtime.h>
@@ -242,16 +247,24 @@ k_scan_add(uint32_t* __restrict__ out, long n, const uint32_t* __restrict__ bsum
         if (base + k < n) out[base + k] += add;
 }
 
-// Move every record of particle i to its sorted slot offsets[key] + rank.  All
-// words are loaded before any is stored: interleaved, each load would wait for
-// the store before it (the record arrays are not known to be disjoint), one
-// memory round trip per word.
+// Sorted order: the particle in storage slot i goes to bin position
+// offsets[key] + rank.
 __global__ void __launch_bounds__(kBlock)
-k_permute(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ ranks,
-          const uint32_t* __restrict__ offsets, long P, Records rec) {
+k_index(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ ranks,
+        const uint32_t* __restrict__ offsets, long P, uint32_t* __restrict__ ord) {
     const long i = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (i >= P) return;
-    const uint32_t key = keys[i], rank = ranks[i];
+    if (i < P) ord[offsets[keys[i]] + ranks[i]] = (uint32_t)i;
+}
+
+// Compaction: record k of every dst array <- record ord[k] of its src array,
+// then ord[k] = k.  All words are loaded before any is stored: interleaved, each
+// load would wait for the store before it (the record arrays are not known to
+// be disjoint), one memory round trip per word.
+__global__ void __launch_bounds__(kBlock)
+k_compact(uint32_t* __restrict__ ord, long P, Records rec) {
+    const long k = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (k >= P) return;
+    const long i = ord[k];
     uint32_t buf[6][3];
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
@@ -259,21 +272,21 @@ k_permute(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ ranks,
             const int w = rec.words[a];
             const uint32_t* src = rec.src[a] + i * w;
 #pragma unroll
-            for (int k = 0; k < 3; ++k)
-                if (k < w) buf[a][k] = src[k];
+            for (int j = 0; j < 3; ++j)
+                if (j < w) buf[a][j] = src[j];
         }
     }
-    const long slot = offsets[key] + rank;
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
         if (a < rec.n) {
             const int w = rec.words[a];
-            uint32_t* dst = rec.dst[a] + slot * w;
+            uint32_t* dst = rec.dst[a] + k * w;
 #pragma unroll
-            for (int k = 0; k < 3; ++k)
-                if (k < w) dst[k] = buf[a][k];
+            for (int j = 0; j < 3; ++j)
+                if (j < w) dst[j] = buf[a][j];
         }
     }
+    ord[k] = (uint32_t)k;
 }
 
 // ------------------------------------------------------------- scatter
@@ -388,7 +401,8 @@ template <int T, bool VEC>
 __global__ void __launch_bounds__(scatter_threads())
 k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, float coeff,
                const unsigned* __restrict__ vmax_bits, Lattice L, int nt,
-               const uint32_t* __restrict__ offsets, float* __restrict__ out, long outStride) {
+               const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ord,
+               float* __restrict__ out, long outStride) {
     constexpr int T3 = T * T * T, NTH = scatter_threads();
     static_assert(T % 4 == 0, "the write-out handles four cells of a row at a time");
     __shared__ __align__(16) unsigned long long acc[T3];
@@ -433,23 +447,30 @@ k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, 
     for (int comp = 0; comp < NC; ++comp) {
         for (int c = threadIdx.x; c < T3 / 2; c += NTH) acc2[c] = make_ulonglong2(0ull, 0ull);
         __syncthreads();
-        // one flat index space over the 20 ranges, so every lane has work; the
-        // next particle's record is loaded before this one's atomics are issued
-        uint32_t nx[3] = {0u, 0u, 0u};
-        float nv = 0.f;
-        auto fetch = [&](uint32_t kk) {
+        // one flat index space over the 20 ranges, so every lane has work.  A
+        // particle's storage slot is loaded two iterations ahead and its record
+        // one iteration ahead, so neither load is waited for before the atomics
+        // of the particle in hand are issued
+        auto slot = [&](uint32_t kk) {
             int r = 0;
             while (pre[r + 1] <= kk) ++r;
-            const long p = rs[r] + (kk - pre[r]);   // particles are stored in bin order
-#pragma unroll
-            for (int a = 0; a < 3; ++a) nx[a] = xq[3 * p + a];
-            if (VEC) nv = vals[3 * p + comp];
+            return ord[rs[r] + (kk - pre[r])];
         };
-        if (threadIdx.x < total) fetch(threadIdx.x);
+        uint32_t nx[3] = {0u, 0u, 0u};
+        float nv = 0.f;
+        auto fetch = [&](uint32_t p) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) nx[a] = xq[3 * (long)p + a];
+            if (VEC) nv = vals[3 * (long)p + comp];
+        };
+        uint32_t ns = 0;   // slot of the particle after the next
+        if (threadIdx.x < total) fetch(slot(threadIdx.x));
+        if (threadIdx.x + NTH < total) ns = slot(threadIdx.x + NTH);
         for (uint32_t k = threadIdx.x; k < total; k += NTH) {
             const uint32_t cur[3] = {nx[0], nx[1], nx[2]};
             const float cv = nv;
-            if (k + NTH < total) fetch(k + NTH);
+            if (k + NTH < total) fetch(ns);
+            if (k + 2 * NTH < total) ns = slot(k + 2 * NTH);
             deposit<T, VEC>(acc, cur, VEC ? amp * cv : amp, e, L, lo);   // densities are >= 0
         }
         __syncthreads();
@@ -485,8 +506,8 @@ k_absmax(const float* __restrict__ v, long n, unsigned* __restrict__ out) {
 //
 // Gathers run one work-group per tile, like the scatter: the (T+1)^3 mesh
 // values the tile's particles can touch are loaded into LDS with coalesced
-// rows, then the particles of the tile's bin (contiguous in the sorted
-// records) interpolate from LDS.  The interpolation uses explicitly rounded
+// rows, then the particles of the tile's bin (through the sorted order)
+// interpolate from LDS.  The interpolation uses explicitly rounded
 // operations in a fixed order, so the forward gather and the reverse-time
 // re-gather produce the same bits.
 
@@ -510,6 +531,7 @@ struct GatherArgs {
     float* xi;            // kUnkickVjp, kWgrad
     float* pi;            // kWgrad
     double* partials;     // one per tile (nullable)
+    const uint32_t* ord;  // storage slot of each bin position
     unsigned* ovf;        // kKickDrift: set to 1 when a momentum leaves the int32 range
 };
 
@@ -517,6 +539,142 @@ struct GatherArgs {
 // work-groups per CU), so those modes use larger work-groups to keep more waves
 // in flight.
 constexpr int gather_threads(int mode) { return mode == kWgrad ? kBlock : 4 * kBlock; }
+
+// A particle's inputs, loaded before any of its outputs is stored (a load after
+// a store to an array that may alias it would wait a full memory round trip).
+struct GatherRec {
+    uint32_t x[3];
+    int32_t pm[3];
+    float xin[3], pin[3];
+};
+
+template <int MODE>
+__device__ __forceinline__ void gather_load(const GatherArgs& A, uint32_t p, GatherRec& r) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) r.x[a] = A.xq[3 * p + a];
+    if constexpr (MODE == kKickDrift) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) r.pm[a] = A.pq[3 * p + a];
+    } else if constexpr (MODE == kUnkickVjp) {
+        if (A.pq) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) r.pm[a] = A.pq[3 * p + a];
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            r.pin[a] = A.pi_in[3 * p + a];
+            r.xin[a] = A.xi[3 * p + a];
+        }
+    } else if constexpr (MODE == kWgrad) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) r.xin[a] = A.xi[3 * p + a];
+        if (A.flag == 1) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                r.pm[a] = A.pq[3 * p + a];
+                r.pin[a] = A.pi[3 * p + a];
+            }
+        }
+    }
+}
+
+// Interpolates the tile's LDS meshes mf at particle p and applies the mode's
+// update; returns the particle's term of the mode's FP64 sum.
+template <int T, int MODE>
+__device__ __forceinline__ double gather_apply(const GatherArgs& A, const Lattice& L,
+                                               const float* mf, const int lo[3], uint32_t p,
+                                               const GatherRec& r) {
+    constexpr int NM = MODE == kWgrad ? 1 : 3;
+    constexpr int TH = T + 1, TH3 = TH * TH * TH;
+    const int mask = L.ng - 1;
+    const float ic = L.inv_cell;
+    int ii[3];
+    float t[3];
+    locate(r.x, L, ii, t);
+    int b[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) b[a] = (ii[a] - lo[a]) & mask;   // in [0, T)
+    float F[NM] = {0.f}, G[NM][3] = {{0.f}};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int c0 = c >> 2, c1 = (c >> 1) & 1, c2 = c & 1;
+        const int li = ((b[0] + c0) * TH + b[1] + c1) * TH + b[2] + c2;
+        const float a0 = c0 ? t[0] : 1.f - t[0];
+        const float a1 = c1 ? t[1] : 1.f - t[1];
+        const float a2 = c2 ? t[2] : 1.f - t[2];
+        const float w = __fmul_rn(__fmul_rn(a0, a1), a2);
+        const float d0 = c0 ? ic : -ic, d1 = c1 ? ic : -ic, d2 = c2 ? ic : -ic;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            const float f = mf[m * TH3 + li];
+            if constexpr (MODE != kWgrad) F[m] = __fmaf_rn(w, f, F[m]);
+            if constexpr (MODE == kUnkickVjp || MODE == kWgrad) {
+                G[m][0] += d0 * a1 * a2 * f;
+                G[m][1] += a0 * d1 * a2 * f;
+                G[m][2] += a0 * a1 * d2 * f;
+            }
+        }
+    }
+    double acc = 0.0;
+    if constexpr (MODE == kKickDrift) {
+        // p + increment in 64 bits: a sum or an increment outside the int32
+        // range (or a non-finite force) would wrap silently, so it is flagged
+        int32_t m[3];
+        bool bad = false;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float q = kick_raw(A.coeff, F[a], L);
+            const long long sum = (long long)r.pm[a] + __float2int_rn(q);
+            m[a] = (int32_t)sum;
+            bad = bad || !(fabsf(q) < 2.0e9f) || sum != (long long)m[a];
+        }
+        if (bad && A.ovf) atomicOr(A.ovf, 1u);
+        if (A.ck_x) {
+            const long q = A.id[p];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                A.ck_x[3 * q + a] = r.x[a];
+                A.ck_p[3 * q + a] = m[a];
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            A.pq[3 * p + a] = m[a];
+            if (A.flag) A.xq[3 * p + a] = r.x[a] + drift_units(A.drift, m[a], L);
+        }
+    } else if constexpr (MODE == kForce) {
+        const long q = A.id[p];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) A.out[3 * q + a] = F[a];
+    } else if constexpr (MODE == kUnkickVjp) {
+        if (A.pq) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) A.pq[3 * p + a] = r.pm[a] - kick_units(A.coeff, F[a], L);
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            A.xi[3 * p + a] =
+                r.xin[a] + A.coeff * (r.pin[0] * G[0][a] + r.pin[1] * G[1][a] + r.pin[2] * G[2][a]);
+        acc = (double)r.pin[0] * F[0] + (double)r.pin[1] * F[1] + (double)r.pin[2] * F[2];
+    } else {   // kWgrad
+        float xv[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            xv[a] = r.xin[a] + A.coeff * G[0][a];
+            A.xi[3 * p + a] = xv[a];
+        }
+        if (A.flag == 1) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int32_t m = r.pm[a];
+                acc += (double)xv[a] * ((double)m * L.mom_unit);
+                A.pi[3 * p + a] = r.pin[a] + A.drift * xv[a];
+                A.xq[3 * p + a] = r.x[a] - drift_units(A.drift, m, L);
+            }
+        }
+    }
+    return acc;
+}
 
 template <int T, int MODE>
 __global__ void __launch_bounds__(gather_threads(MODE), MODE == kWgrad ? 1 : 8)
@@ -532,6 +690,15 @@ k_gather_tile(GatherArgs A, Lattice L, int nt, const uint32_t* __restrict__ offs
     const int mask = L.ng - 1;
     double acc = 0.0;
     if (pbeg < pend) {   // uniform across the work-group
+        // this thread's first particle: its slot and inputs are loaded ahead of
+        // the mesh tile, so their latency overlaps the tile's
+        const uint32_t k0 = pbeg + threadIdx.x;
+        uint32_t p0 = 0;
+        GatherRec r0;
+        if (k0 < pend) {
+            p0 = A.ord[k0];
+            gather_load<MODE>(A, p0, r0);
+        }
         for (int c = threadIdx.x; c < TH3; c += NTH) {
             const int l2 = c % TH, l1 = (c / TH) % TH, l0 = c / (TH * TH);
             const int i0 = (lo[0] + l0) & mask, i1 = (lo[1] + l1) & mask;
@@ -541,122 +708,12 @@ k_gather_tile(GatherArgs A, Lattice L, int nt, const uint32_t* __restrict__ offs
             for (int m = 0; m < NM; ++m) mf[m * TH3 + c] = A.mesh[m * A.mStride + g];
         }
         __syncthreads();
-        const float ic = L.inv_cell;
-        for (uint32_t p = pbeg + threadIdx.x; p < pend; p += NTH) {
-            uint32_t x[3] = {A.xq[3 * p], A.xq[3 * p + 1], A.xq[3 * p + 2]};
-            // every other input of this particle is loaded before any store: a
-            // load after a store to an array that may alias it would wait a full
-            // memory round trip
-            int32_t pm[3] = {0, 0, 0};
-            float xin[3] = {0.f, 0.f, 0.f}, pin[3] = {0.f, 0.f, 0.f};
-            if constexpr (MODE == kKickDrift) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) pm[a] = A.pq[3 * p + a];
-            } else if constexpr (MODE == kUnkickVjp) {
-                if (A.pq) {
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) pm[a] = A.pq[3 * p + a];
-                }
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    pin[a] = A.pi_in[3 * p + a];
-                    xin[a] = A.xi[3 * p + a];
-                }
-            } else if constexpr (MODE == kWgrad) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) xin[a] = A.xi[3 * p + a];
-                if (A.flag == 1) {
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        pm[a] = A.pq[3 * p + a];
-                        pin[a] = A.pi[3 * p + a];
-                    }
-                }
-            }
-            int ii[3];
-            float t[3];
-            locate(x, L, ii, t);
-            int b[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) b[a] = (ii[a] - lo[a]) & mask;   // in [0, T)
-            float F[NM] = {0.f}, G[NM][3] = {{0.f}};
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const int c0 = c >> 2, c1 = (c >> 1) & 1, c2 = c & 1;
-                const int li = ((b[0] + c0) * TH + b[1] + c1) * TH + b[2] + c2;
-                const float a0 = c0 ? t[0] : 1.f - t[0];
-                const float a1 = c1 ? t[1] : 1.f - t[1];
-                const float a2 = c2 ? t[2] : 1.f - t[2];
-                const float w = __fmul_rn(__fmul_rn(a0, a1), a2);
-                const float d0 = c0 ? ic : -ic, d1 = c1 ? ic : -ic, d2 = c2 ? ic : -ic;
-#pragma unroll
-                for (int m = 0; m < NM; ++m) {
-                    const float f = mf[m * TH3 + li];
-                    if constexpr (MODE != kWgrad) F[m] = __fmaf_rn(w, f, F[m]);
-                    if constexpr (MODE == kUnkickVjp || MODE == kWgrad) {
-                        G[m][0] += d0 * a1 * a2 * f;
-                        G[m][1] += a0 * d1 * a2 * f;
-                        G[m][2] += a0 * a1 * d2 * f;
-                    }
-                }
-            }
-            if constexpr (MODE == kKickDrift) {
-                // p + increment in 64 bits: a sum or an increment outside the int32
-                // range (or a non-finite force) would wrap silently, so it is flagged
-                int32_t m[3];
-                bool bad = false;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const float q = kick_raw(A.coeff, F[a], L);
-                    const long long sum = (long long)pm[a] + __float2int_rn(q);
-                    m[a] = (int32_t)sum;
-                    bad = bad || !(fabsf(q) < 2.0e9f) || sum != (long long)m[a];
-                }
-                if (bad && A.ovf) atomicOr(A.ovf, 1u);
-                if (A.ck_x) {
-                    const long q = A.id[p];
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        A.ck_x[3 * q + a] = x[a];
-                        A.ck_p[3 * q + a] = m[a];
-                    }
-                }
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    A.pq[3 * p + a] = m[a];
-                    if (A.flag) A.xq[3 * p + a] = x[a] + drift_units(A.drift, m[a], L);
-                }
-            } else if constexpr (MODE == kForce) {
-                const long q = A.id[p];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) A.out[3 * q + a] = F[a];
-            } else if constexpr (MODE == kUnkickVjp) {
-                if (A.pq) {
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) A.pq[3 * p + a] = pm[a] - kick_units(A.coeff, F[a], L);
-                }
-                const float pv[3] = {pin[0], pin[1], pin[2]};
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    A.xi[3 * p + a] = xin[a] + A.coeff * (pv[0] * G[0][a] + pv[1] * G[1][a] + pv[2] * G[2][a]);
-                acc += (double)pv[0] * F[0] + (double)pv[1] * F[1] + (double)pv[2] * F[2];
-            } else {   // kWgrad
-                float xv[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    xv[a] = xin[a] + A.coeff * G[0][a];
-                    A.xi[3 * p + a] = xv[a];
-                }
-                if (A.flag == 1) {
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        const int32_t m = pm[a];
-                        acc += (double)xv[a] * ((double)m * L.mom_unit);
-                        A.pi[3 * p + a] = pin[a] + A.drift * xv[a];
-                        A.xq[3 * p + a] = x[a] - drift_units(A.drift, m, L);
-                    }
-                }
-            }
+        if (k0 < pend) acc += gather_apply<T, MODE>(A, L, mf, lo, p0, r0);
+        for (uint32_t k = k0 + NTH; k < pend; k += NTH) {   // bins larger than the work-group
+            const uint32_t p = A.ord[k];
+            GatherRec r;
+            gather_load<MODE>(A, p, r);
+            acc += gather_apply<T, MODE>(A, L, mf, lo, p, r);
         }
     }
     if (A.partials) {
@@ -1127,7 +1184,7 @@ void launch_zero(void* p, size_t bytes, hipStream_t s) {
     hipLaunchKernelGGL(k_zero, dim3(grid_for(n)), dim3(kBlock), 0, s, (uint32_t*)p, n);
 }
 
-void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, const Records& rec, hipStream_t s) {
+void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, hipStream_t s) {
     const long P = (long)L.np * L.np * L.np;
     const long nk = b.nkeys();
     launch_zero(b.counts, (nk + 1) * sizeof(uint32_t), s);
@@ -1140,8 +1197,13 @@ void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, const Records& re
     hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kScanThreads), 0, s, b.scan_tmp, nb);
     hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kScanThreads), 0, s, b.offsets, n,
                        b.scan_tmp);
-    hipLaunchKernelGGL(k_permute, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       b.keys, b.ranks, b.offsets, P, rec);
+    hipLaunchKernelGGL(k_index, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       b.keys, b.ranks, b.offsets, P, b.ord);
+}
+
+void launch_compact(Bins& b, const Records& rec, long P, hipStream_t s) {
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       b.ord, P, rec);
 }
 
 template <bool VEC>
@@ -1152,15 +1214,15 @@ static void scatter_dispatch(const uint32_t* xq, const float* v, float coeff, co
     switch (b.tile) {
         case 4:
             hipLaunchKernelGGL((k_scatter_tile<4, VEC>), dim3(ntiles), dim3(scatter_threads()), 0, s, xq, v,
-                               coeff, vmax, L, b.nt, b.offsets, out, outStride);
+                               coeff, vmax, L, b.nt, b.offsets, b.ord, out, outStride);
             break;
         case 8:
             hipLaunchKernelGGL((k_scatter_tile<8, VEC>), dim3(ntiles), dim3(scatter_threads()), 0, s, xq, v,
-                               coeff, vmax, L, b.nt, b.offsets, out, outStride);
+                               coeff, vmax, L, b.nt, b.offsets, b.ord, out, outStride);
             break;
         default:
             hipLaunchKernelGGL((k_scatter_tile<16, VEC>), dim3(ntiles), dim3(scatter_threads()), 0, s, xq, v,
-                               coeff, vmax, L, b.nt, b.offsets, out, outStride);
+                               coeff, vmax, L, b.nt, b.offsets, b.ord, out, outStride);
             break;
     }
 }
@@ -1181,8 +1243,9 @@ void launch_scatter_vec(const uint32_t* xq, const float* v, float coeff, unsigne
 }
 
 template <int MODE>
-static void gather_dispatch(const GatherArgs& A, const Lattice& L, const Bins& b, hipStream_t s) {
+static void gather_dispatch(GatherArgs A, const Lattice& L, const Bins& b, hipStream_t s) {
     const unsigned ntiles = (unsigned)b.nt * b.nt * b.nt;
+    A.ord = b.ord;
     switch (b.tile) {
         case 4:
             hipLaunchKernelGGL((k_gather_tile<4, MODE>), dim3(ntiles), dim3(gather_threads(MODE)), 0, s, A, L, b.nt,

@@ -104,7 +104,7 @@ struct Plan {
     size_t total = 0;
     size_t cplx, disp, mom, xi, pi, disp2, mom2, xi2, pi2, id, id2, fin_disp, fin_mom, s_ic, tmpv,
         noise, ckpt;
-    size_t counts, offsets, keys, ranks, scan_tmp;
+    size_t counts, offsets, keys, ranks, ord, scan_tmp;
     size_t radial_f, radial_ic, radial_ic_dom, radial_lpt, losstab, tw, tw_stages, partials, sums, maxbits,
         pkbins;
     size_t theta, gtheta, fbar, mlp_scratch, ovf;
@@ -150,6 +150,7 @@ struct Plan {
         offsets = take((nkeys + 1) * sizeof(uint32_t));
         keys = take((size_t)P * sizeof(uint32_t));
         ranks = take((size_t)P * sizeof(uint32_t));
+        ord = take((size_t)P * sizeof(uint32_t));
         scan_tmp = take(scan_tmp_elems(nkeys) * sizeof(uint32_t));
         radial_f = take(ntab_f * sizeof(float));
         radial_ic = take(ntab_p * sizeof(float));
@@ -217,6 +218,9 @@ struct pm_ctx {
     std::vector<double> g_step;     // [3N] dL/d(step_scale) of the last adjoint
     bool have_step_grads = false;
     bool have_forward = false;
+    // sorts since the records were last moved into bin order; kLatticeOrder
+    // after the records were (re)written in lattice order
+    int sorts_since_compact = 0;
     bool have_filter = false;
     std::string err;
     pm_stats stats;
@@ -371,9 +375,26 @@ const float* force_radial(pm_ctx* ctx, double a) {
     return ctx->radial_f;
 }
 
-// Sort the working records by bin (positions, momenta, ids, and with
-// `cotangents` also xi and pi), leaving the bin offsets in ctx->bins.
-void sort_particles(pm_ctx* ctx, bool cotangents) {
+// Records are moved into bin order on every kCompactEvery-th sort, and on the
+// first sort after they were written in lattice order; in between, the sort
+// only rebuilds the bin order (8 bytes written per particle instead of the 28
+// or 52 bytes of its records, read and written).  The particle kernels then
+// read the records through the order, a little less coalesced as particles
+// change bins: measured at 512^3 particles, every 4th sort (bin family 524 ->
+// 290 ms per 1024^3-mesh run, particle kernels +155 ms) beats every 2nd or
+// 8th, and compacting on every sort of the adjoint gains nothing.
+constexpr int kCompactEvery = 4;
+constexpr int kLatticeOrder = 1 << 20;   // forces a compaction
+
+// Bin the working particles (bin offsets and order in ctx->bins); compact the
+// records (positions, momenta, ids, and with `cotangents` also xi and pi) when
+// due.  Returns the bytes moved, for the timing statistics.
+double sort_particles(pm_ctx* ctx, bool cotangents) {
+    const double P = (double)ctx->P;
+    launch_bin(ctx->xq, ctx->lat, ctx->bins, ctx->stream);
+    double bytes = 32.0 * P;   // positions, keys and ranks, order
+    if (++ctx->sorts_since_compact <= kCompactEvery) return bytes;
+    ctx->sorts_since_compact = 1;
     Records rec;
     rec.add(ctx->xq, ctx->xq_alt, 3);
     rec.add(ctx->pq, ctx->pq_alt, 3);
@@ -382,7 +403,7 @@ void sort_particles(pm_ctx* ctx, bool cotangents) {
         rec.add(ctx->xi, ctx->xi_alt, 3);
         rec.add(ctx->pi, ctx->pi_alt, 3);
     }
-    launch_bin(ctx->xq, ctx->lat, ctx->bins, rec, ctx->stream);
+    launch_compact(ctx->bins, rec, ctx->P, ctx->stream);
     std::swap(ctx->xq, ctx->xq_alt);
     std::swap(ctx->pq, ctx->pq_alt);
     std::swap(ctx->id, ctx->id_alt);
@@ -390,7 +411,11 @@ void sort_particles(pm_ctx* ctx, bool cotangents) {
         std::swap(ctx->xi, ctx->xi_alt);
         std::swap(ctx->pi, ctx->pi_alt);
     }
+    return bytes + (cotangents ? 112.0 : 64.0) * P;
 }
+
+// The working records were just written in lattice order.
+void records_in_lattice_order(pm_ctx* ctx) { ctx->sorts_since_compact = kLatticeOrder; }
 
 // PM force meshes of the working particles: sort into bins, delta -> C0
 // (x,y-transformed spectrum left in C0), F~_j real meshes in C1..C3.
@@ -399,7 +424,7 @@ void compute_force(pm_ctx* ctx, double a, bool cotangents) {
     const int ng = ctx->ng, cs = ctx->cs;
     const long cst = ctx->plan.cplx_elems;
     const double r = mesh_r(ng), c = mesh_c(ng), P = (double)ctx->P;
-    { KTimer t(ctx, PM_K_BIN, (cotangents ? 64 : 40) * P); sort_particles(ctx, cotangents); }
+    { KTimer t(ctx, PM_K_BIN, 0); t.bytes = sort_particles(ctx, cotangents); }
     { KTimer t(ctx, PM_K_SCATTER, 12 * P + r);
       launch_scatter_density(ctx->xq, ctx->lat, ctx->bins, ctx->creal(0), s); }
     { KTimer t(ctx, PM_K_FFT_X, r + c); launch_fft_x_r2c(ctx->C[0], ng, cs, 1, cst, ctx->twd, s); }
@@ -777,6 +802,7 @@ int pm_init(const pm_config* cfg, const pm_cosmology* cosmo, void* workspace, si
     ctx->bins.offsets = ctx->at<uint32_t>(p.offsets);
     ctx->bins.keys = ctx->at<uint32_t>(p.keys);
     ctx->bins.ranks = ctx->at<uint32_t>(p.ranks);
+    ctx->bins.ord = ctx->at<uint32_t>(p.ord);
     ctx->bins.scan_tmp = ctx->at<uint32_t>(p.scan_tmp);
     std::memset(&ctx->stats, 0, sizeof(ctx->stats));
     ctx->stats.workspace_bytes = p.total;
@@ -873,6 +899,7 @@ int pm_forward(pm_ctx* ctx, const float* noise, float* disp_out, float* mom_out,
     if (ctx->lpt2()) lpt_second_order(ctx, ctx->noise, ctx->tmpv);
     ic_synthesis(ctx, ctx->noise, ctx->radial_ic, ctx->s_ic, ctx->xq, ctx->pq, ctx->id,
                  ctx->lpt2() ? ctx->tmpv : nullptr);
+    records_in_lattice_order(ctx);
     for (int n = 0; n <= N; ++n) {
         compute_force(ctx, sc.a[n], false);
         const double kick = (n > 0 ? sc.kick_b[n - 1] : 0.0) + (n < N ? sc.kick_a[n] : 0.0);
@@ -932,6 +959,7 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
     PM_TRY(copy_d2d(ctx, ctx->xq, ctx->fin_x, vec));
     PM_TRY(copy_d2d(ctx, ctx->pq, ctx->fin_p, vec));
     launch_iota(ctx->id, P, s);   // records start in lattice order
+    records_in_lattice_order(ctx);
     launch_zero(ctx->sums, (2 * (size_t)N + 2 + kExtraSlots) * sizeof(double), s);
     launch_zero(ctx->maxbits, kExtraSlots * sizeof(unsigned), s);
     if (c.filter) launch_zero(ctx->gtheta, kNParam * sizeof(float), s);
@@ -982,6 +1010,7 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
             std::swap(ctx->xi, ctx->xi_alt);
             std::swap(ctx->pi, ctx->pi_alt);
             launch_iota(ctx->id, P, s);
+            records_in_lattice_order(ctx);
             ++nck;
         }
         // recompute F(x_n); un-kick and (i) at x_n
@@ -1105,6 +1134,7 @@ int pm_initial_conditions(pm_ctx* ctx, const float* noise, float* disp_out, floa
     if (ctx->lpt2()) lpt_second_order(ctx, noise, ctx->tmpv);
     ic_synthesis(ctx, noise, ctx->radial_ic, ctx->s_ic, ctx->xq, ctx->pq, ctx->id,
                  ctx->lpt2() ? ctx->tmpv : nullptr);
+    records_in_lattice_order(ctx);
     {
         KTimer t(ctx, PM_K_OTHER, 0);
         launch_from_fixed(ctx->xq, ctx->pq, ctx->id, ctx->lat, disp_out, mom_out, ctx->stream);
@@ -1238,6 +1268,7 @@ int pm_density(pm_ctx* ctx, const float* disp, float* dens) {
     PM_TRY(ctx_check(ctx));
     if (!disp || !dens) return ctx->fail(PM_EINVAL, "disp and dens are required");
     launch_to_fixed(disp, ctx->xq, ctx->id, ctx->lat, ctx->stream);
+    records_in_lattice_order(ctx);
     sort_particles(ctx, false);
     launch_scatter_density(ctx->xq, ctx->lat, ctx->bins, ctx->creal(0), ctx->stream);
     launch_from_pitched(ctx->creal(0), dens, ctx->ng, ctx->lat.rp, ctx->stream);
@@ -1249,6 +1280,7 @@ int pm_force(pm_ctx* ctx, const float* disp, double a, float* force) {
     if (!disp || !force) return ctx->fail(PM_EINVAL, "disp and force are required");
     if (ctx->cfg.filter && !ctx->have_filter) return ctx->fail(PM_ESTATE, "pm_set_filter not called");
     launch_to_fixed(disp, ctx->xq, ctx->id, ctx->lat, ctx->stream);
+    records_in_lattice_order(ctx);
     compute_force(ctx, a, false);
     launch_gather_force(ctx->xq, ctx->id, ctx->creal(1), ctx->creal_stride(), ctx->lat, ctx->bins,
                         force, ctx->stream);
@@ -1261,6 +1293,7 @@ int pm_force_vjp(pm_ctx* ctx, const float* disp, double a, const float* v, float
     if (ctx->cfg.filter && !ctx->have_filter) return ctx->fail(PM_ESTATE, "pm_set_filter not called");
     hipStream_t s = ctx->stream;
     launch_to_fixed(disp, ctx->xq, ctx->id, ctx->lat, s);
+    records_in_lattice_order(ctx);
     compute_force(ctx, a, false);
     // v and xi in the records' (sorted) order
     launch_permute_by_id(v, ctx->id, ctx->pi, ctx->P, 0, s);

@@ -92,7 +92,7 @@ def family(sym: str, ng: int):
         mode = targs[1] if len(targs) > 1 else ""
         return {"0": ("gather", "48P+3r"), "1": ("gather", "24P+3r"),
                 "2": ("unkick_vjp", "72P+3r"), "3": ("wgrad", "84P+r")}.get(mode, (None, None))
-    if base in ("k_bin_count", "k_scan_local", "k_scan_bsum", "k_scan_add", "k_permute"):
+    if base in ("k_bin_count", "k_scan_local", "k_scan_bsum", "k_scan_add", "k_index", "k_compact"):
         return "bin", None
     if base.startswith("k_mlp") or base == "k_adam":
         return "mlp", None
