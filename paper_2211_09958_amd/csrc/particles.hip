@@ -699,13 +699,24 @@ k_gather_tile(GatherArgs A, Lattice L, int nt, const uint32_t* __restrict__ offs
             p0 = A.ord[k0];
             gather_load<MODE>(A, p0, r0);
         }
-        for (int c = threadIdx.x; c < TH3; c += NTH) {
-            const int l2 = c % TH, l1 = (c / TH) % TH, l0 = c / (TH * TH);
-            const int i0 = (lo[0] + l0) & mask, i1 = (lo[1] + l1) & mask;
-            const long row = A.dense ? (long)i0 * L.ng + i1 : mesh_row(i0, i1, L.ng);
-            const long g = row * A.pitch + ((lo[2] + l2) & mask);
+        // the tile as NM (T+1)^2 columns along axis 0, one per thread: rows
+        // i0 = lo0 .. lo0 + T - 1 lie a fixed number of storage rows apart (one
+        // row-block side, or Ng in plain row order), so a column costs an
+        // address add per value; row lo0 + T (which may wrap) is addressed apart
+        const long step = (A.dense ? (long)L.ng : (1L << row_block_log2(L.ng))) * A.pitch;
+        const int i0h = (lo[0] + T) & mask;
+        for (int u = threadIdx.x; u < NM * TH * TH; u += NTH) {
+            const int m = u / (TH * TH), pr = u - m * (TH * TH);
+            const int l1 = pr / TH, l2 = pr - l1 * TH;
+            const int i1 = (lo[1] + l1) & mask, i2 = (lo[2] + l2) & mask;
+            const float* src = A.mesh + m * A.mStride + i2;
+            const long row0 = A.dense ? (long)lo[0] * L.ng + i1 : mesh_row(lo[0], i1, L.ng);
+            const long rowh = A.dense ? (long)i0h * L.ng + i1 : mesh_row(i0h, i1, L.ng);
+            float* dst = mf + m * TH3 + pr;
+            const float* col = src + row0 * A.pitch;
 #pragma unroll
-            for (int m = 0; m < NM; ++m) mf[m * TH3 + c] = A.mesh[m * A.mStride + g];
+            for (int l0 = 0; l0 < T; ++l0) dst[l0 * TH * TH] = col[l0 * step];
+            dst[T * TH * TH] = src[rowh * A.pitch];
         }
         __syncthreads();
         if (k0 < pend) acc += gather_apply<T, MODE>(A, L, mf, lo, p0, r0);
