@@ -225,6 +225,10 @@ def main():
     if shown:
         labels = [label for label, _ in res[shown[0]]]
         lines += ["", "## Per kernel symbol: resources (from the kernel trace)", "",
+                  "Register counts as the trace records them; for these wave64 kernels its "
+                  "VGPR figure is half the `.vgpr_count` of the code object's metadata (for "
+                  "example 249 for `k_grad_z_pipe<1024>`, recorded as 128): waves per SIMD = "
+                  "512 / (2 x VGPRs), at most 8.", "",
                   "| kernel | " + " | ".join(labels) + " |",
                   "|---|" + "---|" * len(labels)]
         for s in shown:
