@@ -115,7 +115,12 @@ struct Records {
 // offsets and the sorted order b.ord (bin k of the offsets holds the particles
 // in storage slots ord[offsets[k]], ..., ord[offsets[k + 1] - 1]); the records
 // stay where they are.
-void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, hipStream_t s);
+// With `counted`, the counts, keys and ranks were already produced by the
+// gather that moved the particles (see count_bins below) and only the scan and
+// the order remain.
+void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, bool counted, hipStream_t s);
+// Zeroes the bin counts ahead of a gather that counts the particles it moves.
+void launch_bin_zero(Bins& b, hipStream_t s);
 // Moves every record array from src to dst in the order b.ord and resets b.ord
 // to the identity (each bin then a contiguous range of the records).
 void launch_compact(Bins& b, const Records& rec, long P, hipStream_t s);
@@ -138,10 +143,13 @@ long wgrad_partials(const Bins& b);
 // F = gather(force meshes), p += kick F, optional checkpoint copy of (x, p) in
 // lattice order (by id), then x += drift p (if do_drift).  *ovf (nullable) is
 // set to 1 when a new momentum does not fit the int32 fixed-point range.
+// With count_bins (and do_drift), the drifted particles are also counted into
+// b's counts, keys and ranks for the next launch_bin(counted = true); the
+// counts must have been zeroed (launch_bin_zero) after the last scan.
 void launch_gather_kick_drift(uint32_t* xq, int32_t* pq, const uint32_t* id, const float* fmesh,
                               long fStride, const Lattice& L, const Bins& b, float kick,
                               float drift, int do_drift, uint32_t* ck_x, int32_t* ck_p,
-                              unsigned* ovf, hipStream_t s);
+                              unsigned* ovf, bool count_bins, hipStream_t s);
 // out[id[p]][j] = Sum w F_j (lattice order).
 void launch_gather_force(const uint32_t* xq, const uint32_t* id, const float* fmesh, long fStride,
                          const Lattice& L, const Bins& b, float* out, hipStream_t s);
@@ -154,9 +162,11 @@ void launch_unkick_vjp(const uint32_t* xq, int32_t* pq, const float* fmesh, long
 // order of layout.h, or in plain order when dense).  mode 1 also does the rest
 // of a reverse step: partials Sum xi . p, pi += drift xi, x -= drift p (exact
 // inverse of the forward drift); mode 2 only updates xi.
+// count_bins (mode 1): the un-drifted particles are counted as in
+// launch_gather_kick_drift.
 void launch_wgrad(const float* mesh, long pitch, float g_scale, uint32_t* xq, const int32_t* pq,
                   float* xi, float* pi, const Lattice& L, const Bins& b, float drift, int mode,
-                  double* partials, hipStream_t s, bool dense = false);
+                  double* partials, hipStream_t s, bool dense = false, bool count_bins = false);
 // Displacements (float, Mpc/h, lattice order) -> fixed-point positions q + s
 // in lattice order, id = identity.
 void launch_to_fixed(const float* disp, uint32_t* xq, uint32_t* id, const Lattice& L,

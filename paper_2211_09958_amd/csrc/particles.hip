@@ -132,30 +132,29 @@ __device__ __forceinline__ void block_max_to(float m, unsigned* out) {
 
 // ------------------------------------------------------------- binning
 
-__global__ void __launch_bounds__(kBlock)
-k_bin_count(const uint32_t* __restrict__ xq, Lattice L, int tile, int nt, long P,
-            uint32_t* __restrict__ counts, uint32_t* __restrict__ keys,
-            uint32_t* __restrict__ ranks) {
-    const long i = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    const bool valid = i < P;
-    uint32_t key = 0xffffffffu;
-    if (valid) {
-        int ii[3];
-        float t[3];
-        locate(xq + 3 * i, L, ii, t);
-        // tile is a power of two and ii >= 0: shifts and masks instead of the
-        // (emulated) integer division and remainder by a run-time value
-        const int tl = __ffs(tile) - 1, tm = tile - 1;
-        const uint32_t tix = morton3(ii[0] >> tl, ii[1] >> tl, ii[2] >> tl);
-        uint32_t cls = (((ii[0] & tm) == tm) << 2) | (((ii[1] & tm) == tm) << 1) |
-                       ((ii[2] & tm) == tm);
-        key = tix * 8 + cls;
-    }
-    // one atomic per distinct key in the wave, all issued together: group the
-    // lanes by key first (no memory traffic), then every group's first lane adds
-    // the group size, and rank = that slot + the lane's place in its group
+// Bin key of a particle at x: its tile (Morton number) times 8 plus its spill
+// class.  tile is a power of two and the node indices are >= 0: shifts and
+// masks instead of the (emulated) integer division and remainder by a
+// run-time value.
+__device__ __forceinline__ uint32_t bin_key(const uint32_t x[3], const Lattice& L, int tile) {
+    int ii[3];
+    float t[3];
+    locate(x, L, ii, t);
+    const int tl = __ffs(tile) - 1, tm = tile - 1;
+    const uint32_t tix = morton3(ii[0] >> tl, ii[1] >> tl, ii[2] >> tl);
+    const uint32_t cls = (((ii[0] & tm) == tm) << 2) | (((ii[1] & tm) == tm) << 1) |
+                         ((ii[2] & tm) == tm);
+    return tix * 8 + cls;
+}
+
+// Counts the particles of the active lanes into counts[key] and returns each
+// one's rank among the particles of its key.  One atomic per distinct key in
+// the wave, all issued together: the lanes are grouped by key first (no memory
+// traffic), then every group's first lane adds the group size, and rank = that
+// slot + the lane's place in its group.  Every active lane must call it.
+__device__ __forceinline__ uint32_t bin_rank(uint32_t key, uint32_t* __restrict__ counts) {
     const int lane = __lane_id();
-    unsigned long long pending = __ballot(valid);
+    unsigned long long pending = __ballot(1);
     unsigned long long mine = 0ull;   // lanes sharing this lane's key
     while (pending) {
         const int leader = __ffsll((long long)pending) - 1;
@@ -164,12 +163,21 @@ k_bin_count(const uint32_t* __restrict__ xq, Lattice L, int tile, int nt, long P
         if ((same >> lane) & 1ull) mine = same;
         pending &= ~same;
     }
-    const int first = valid ? __ffsll((long long)mine) - 1 : lane;
+    const int first = __ffsll((long long)mine) - 1;
     uint32_t base = 0;
-    if (valid && lane == first) base = atomicAdd(&counts[key], (uint32_t)__popcll(mine));
+    if (lane == first) base = atomicAdd(&counts[key], (uint32_t)__popcll(mine));
     base = (uint32_t)__shfl((int)base, first);
-    const uint32_t rank = base + (uint32_t)__popcll(mine & ((1ull << lane) - 1ull));
-    if (valid) {
+    return base + (uint32_t)__popcll(mine & ((1ull << lane) - 1ull));
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_bin_count(const uint32_t* __restrict__ xq, Lattice L, int tile, long P,
+            uint32_t* __restrict__ counts, uint32_t* __restrict__ keys,
+            uint32_t* __restrict__ ranks) {
+    const long i = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i < P) {
+        const uint32_t key = bin_key(xq + 3 * i, L, tile);
+        const uint32_t rank = bin_rank(key, counts);
         keys[i] = key;
         ranks[i] = rank;
     }
@@ -532,6 +540,13 @@ struct GatherArgs {
     float* pi;            // kWgrad
     double* partials;     // one per tile (nullable)
     const uint32_t* ord;  // storage slot of each bin position
+    // kKickDrift with drift, kWgrad flag 1: count the moved particles into the
+    // next sort's bins (count != 0; pointers filled from the bins at launch)
+    int count;
+    uint32_t* bcounts;
+    uint32_t* bkeys;
+    uint32_t* branks;
+    int btile;
     unsigned* ovf;        // kKickDrift: set to 1 when a momentum leaves the int32 range
 };
 
@@ -637,10 +652,18 @@ __device__ __forceinline__ double gather_apply(const GatherArgs& A, const Lattic
                 A.ck_p[3 * q + a] = m[a];
             }
         }
+        uint32_t xn[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
+            xn[a] = r.x[a] + drift_units(A.drift, m[a], L);
             A.pq[3 * p + a] = m[a];
-            if (A.flag) A.xq[3 * p + a] = r.x[a] + drift_units(A.drift, m[a], L);
+            if (A.flag) A.xq[3 * p + a] = xn[a];
+        }
+        if (A.flag && A.count) {
+            const uint32_t key = bin_key(xn, L, A.btile);
+            const uint32_t rank = bin_rank(key, A.bcounts);
+            A.bkeys[p] = key;
+            A.branks[p] = rank;
         }
     } else if constexpr (MODE == kForce) {
         const long q = A.id[p];
@@ -664,12 +687,20 @@ __device__ __forceinline__ double gather_apply(const GatherArgs& A, const Lattic
             A.xi[3 * p + a] = xv[a];
         }
         if (A.flag == 1) {
+            uint32_t xn[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int32_t m = r.pm[a];
                 acc += (double)xv[a] * ((double)m * L.mom_unit);
                 A.pi[3 * p + a] = r.pin[a] + A.drift * xv[a];
-                A.xq[3 * p + a] = r.x[a] - drift_units(A.drift, m, L);
+                xn[a] = r.x[a] - drift_units(A.drift, m, L);
+                A.xq[3 * p + a] = xn[a];
+            }
+            if (A.count) {
+                const uint32_t key = bin_key(xn, L, A.btile);
+                const uint32_t rank = bin_rank(key, A.bcounts);
+                A.bkeys[p] = key;
+                A.branks[p] = rank;
             }
         }
     }
@@ -1195,12 +1226,18 @@ void launch_zero(void* p, size_t bytes, hipStream_t s) {
     hipLaunchKernelGGL(k_zero, dim3(grid_for(n)), dim3(kBlock), 0, s, (uint32_t*)p, n);
 }
 
-void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, hipStream_t s) {
+void launch_bin_zero(Bins& b, hipStream_t s) {
+    launch_zero(b.counts, (b.nkeys() + 1) * sizeof(uint32_t), s);
+}
+
+void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, bool counted, hipStream_t s) {
     const long P = (long)L.np * L.np * L.np;
     const long nk = b.nkeys();
-    launch_zero(b.counts, (nk + 1) * sizeof(uint32_t), s);
-    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       xq, L, b.tile, b.nt, P, b.counts, b.keys, b.ranks);
+    if (!counted) {
+        launch_bin_zero(b, s);
+        hipLaunchKernelGGL(k_bin_count, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           s, xq, L, b.tile, P, b.counts, b.keys, b.ranks);
+    }
     const long n = nk + 1;
     const long nb = (n + kScanChunk - 1) / kScanChunk;
     hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(kScanThreads), 0, s, b.counts,
@@ -1257,6 +1294,12 @@ template <int MODE>
 static void gather_dispatch(GatherArgs A, const Lattice& L, const Bins& b, hipStream_t s) {
     const unsigned ntiles = (unsigned)b.nt * b.nt * b.nt;
     A.ord = b.ord;
+    if (A.count) {   // the bins are read (ord, offsets) before the counts are reused
+        A.bcounts = b.counts;
+        A.bkeys = b.keys;
+        A.branks = b.ranks;
+        A.btile = b.tile;
+    }
     switch (b.tile) {
         case 4:
             hipLaunchKernelGGL((k_gather_tile<4, MODE>), dim3(ntiles), dim3(gather_threads(MODE)), 0, s, A, L, b.nt,
@@ -1279,9 +1322,10 @@ long wgrad_partials(const Bins& b) { return (long)b.nt * b.nt * b.nt; }
 void launch_gather_kick_drift(uint32_t* xq, int32_t* pq, const uint32_t* id, const float* fmesh,
                               long fStride, const Lattice& L, const Bins& b, float kick,
                               float drift, int do_drift, uint32_t* ck_x, int32_t* ck_p,
-                              unsigned* ovf, hipStream_t s) {
+                              unsigned* ovf, bool count_bins, hipStream_t s) {
     GatherArgs A{};
     A.ovf = ovf;
+    A.count = count_bins && do_drift;
     A.xq = xq;
     A.pq = pq;
     A.id = id;
@@ -1326,8 +1370,9 @@ void launch_unkick_vjp(const uint32_t* xq, int32_t* pq, const float* fmesh, long
 
 void launch_wgrad(const float* mesh, long pitch, float g_scale, uint32_t* xq, const int32_t* pq,
                   float* xi, float* pi, const Lattice& L, const Bins& b, float drift, int mode,
-                  double* partials, hipStream_t s, bool dense) {
+                  double* partials, hipStream_t s, bool dense, bool count_bins) {
     GatherArgs A{};
+    A.count = count_bins && mode == 1;
     A.xq = xq;
     A.pq = const_cast<int32_t*>(pq);
     A.mesh = mesh;

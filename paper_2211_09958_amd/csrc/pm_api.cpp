@@ -221,6 +221,8 @@ struct pm_ctx {
     // sorts since the records were last moved into bin order; kLatticeOrder
     // after the records were (re)written in lattice order
     int sorts_since_compact = 0;
+    // the gather that last moved the particles also counted them into the bins
+    bool counts_ready = false;
     bool have_filter = false;
     std::string err;
     pm_stats stats;
@@ -391,8 +393,11 @@ constexpr int kLatticeOrder = 1 << 20;   // forces a compaction
 // due.  Returns the bytes moved, for the timing statistics.
 double sort_particles(pm_ctx* ctx, bool cotangents) {
     const double P = (double)ctx->P;
-    launch_bin(ctx->xq, ctx->lat, ctx->bins, ctx->stream);
-    double bytes = 32.0 * P;   // positions, keys and ranks, order
+    launch_bin(ctx->xq, ctx->lat, ctx->bins, ctx->counts_ready, ctx->stream);
+    // positions read, keys and ranks written and read, order written (the
+    // gather that counted accounts for its own key and rank writes)
+    double bytes = ctx->counts_ready ? 12.0 * P : 32.0 * P;
+    ctx->counts_ready = false;
     if (++ctx->sorts_since_compact <= kCompactEvery) return bytes;
     ctx->sorts_since_compact = 1;
     Records rec;
@@ -415,7 +420,14 @@ double sort_particles(pm_ctx* ctx, bool cotangents) {
 }
 
 // The working records were just written in lattice order.
-void records_in_lattice_order(pm_ctx* ctx) { ctx->sorts_since_compact = kLatticeOrder; }
+void records_in_lattice_order(pm_ctx* ctx) {
+    ctx->sorts_since_compact = kLatticeOrder;
+    ctx->counts_ready = false;
+}
+
+// Zeroes the bin counts for a gather that counts the particles it moves into
+// the next sort's bins.
+void count_next_bins(pm_ctx* ctx) { launch_bin_zero(ctx->bins, ctx->stream); }
 
 // PM force meshes of the working particles: sort into bins, delta -> C0
 // (x,y-transformed spectrum left in C0), F~_j real meshes in C1..C3.
@@ -910,10 +922,15 @@ int pm_forward(pm_ctx* ctx, const float* noise, float* disp_out, float* mom_out,
             ckx = ctx->ckpt + (size_t)slot * 6 * ctx->P;
             ckp = reinterpret_cast<int32_t*>(ckx + 3 * ctx->P);
         }
-        KTimer t(ctx, PM_K_GATHER, (ckx ? 72.0 : 48.0) * ctx->P + 3 * mesh_r(ctx->ng));
+        const bool count = n < N;   // the drifted particles are binned for the next force
+        if (count) count_next_bins(ctx);
+        KTimer t(ctx, PM_K_GATHER,
+                 ((ckx ? 72.0 : 48.0) + (count ? 8.0 : 0.0)) * ctx->P + 3 * mesh_r(ctx->ng));
         launch_gather_kick_drift(ctx->xq, ctx->pq, ctx->id, ctx->creal(1), ctx->creal_stride(),
                                  ctx->lat, ctx->bins, (float)kick,
-                                 n < N ? (float)sc.drift[n] : 0.f, n < N, ckx, ckp, ctx->ovf, s);
+                                 n < N ? (float)sc.drift[n] : 0.f, n < N, ckx, ckp, ctx->ovf,
+                                 count, s);
+        ctx->counts_ready = count;
     }
     {
         KTimer t(ctx, PM_K_OTHER, 0);
@@ -990,9 +1007,12 @@ int pm_adjoint(pm_ctx* ctx, const float* g_dens, const float* g_disp, const floa
         const double c1 = sc.kick_b[n] + (n + 1 < N ? sc.kick_a[n + 1] : 0.0);
         vjp_mesh(ctx, ctx->xq, ctx->pi, (float)c1, sc.a[n + 1]);
         {
-            KTimer t(ctx, PM_K_WGRAD, bytes_wgrad);
+            count_next_bins(ctx);   // the un-drifted particles are binned for F(x_n)
+            KTimer t(ctx, PM_K_WGRAD, bytes_wgrad + 8.0 * P);
             launch_wgrad(ctx->creal(0), ctx->lat.rp, mass, ctx->xq, ctx->pq, ctx->xi, ctx->pi,
-                         ctx->lat, ctx->bins, (float)sc.drift[n], 1, ctx->partials, s);
+                         ctx->lat, ctx->bins, (float)sc.drift[n], 1, ctx->partials, s, false,
+                         true);
+            ctx->counts_ready = true;
         }
         launch_reduce(ctx->partials, nbw, ctx->sums, slotD + n, s);
         // checkpoint: compare the reconstructed (x_n, p_{n+1/2}) and reset to it
