@@ -392,6 +392,52 @@ __device__ __forceinline__ void deposit(unsigned long long* acc, const uint32_t 
     }
 }
 
+// The 8 CIC corners of a particle at x as LDS cells of the tile at lo and
+// weights, with weight 0 for a corner outside the tile; cells packed two to a
+// word (a tile has at most 2^12 cells).  Same arithmetic as deposit.
+template <int T>
+__device__ __forceinline__ void corners(const uint32_t x[3], const Lattice& L, const int lo[3],
+                                        float w[8], uint32_t cell2[4]) {
+    static_assert(T * T * T <= 4096, "cells are packed into 16 bits");
+    const int mask = L.ng - 1;
+    int ii[3];
+    float t[3];
+    locate(x, L, ii, t);
+    int l[3][2];
+    bool in[3][2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            int v = ((ii[a] + c) & mask) - lo[a];
+            if (v < 0) v += L.ng;
+            l[a][c] = v;
+            in[a][c] = v < T;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int c0 = c >> 2, c1 = (c >> 1) & 1, c2 = c & 1;
+        const float w01 = (c0 ? t[0] : 1.f - t[0]) * (c1 ? t[1] : 1.f - t[1]);
+        const float wc = w01 * (c2 ? t[2] : 1.f - t[2]);
+        w[c] = in[0][c0] && in[1][c1] && in[2][c2] ? wc : 0.f;
+        const uint32_t cl = (uint32_t)((l[0][c0] * T + l[1][c1]) * T + l[2][c2]) & 0xffffu;
+        if (c & 1) cell2[c >> 1] |= cl << 16;
+        else cell2[c >> 1] = cl;
+    }
+}
+
+// deposit for corners kept by `corners` (a corner of weight 0 adds nothing).
+__device__ __forceinline__ void deposit_kept(unsigned long long* acc, const float w[8],
+                                             const uint32_t cell2[4], float val, int e) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if (w[c] == 0.f) continue;
+        const uint32_t cl = (c & 1) ? cell2[c >> 1] >> 16 : cell2[c >> 1] & 0xffffu;
+        atomicAdd(&acc[cl], to_fixed64(ldexpf(w[c] * val, e)));
+    }
+}
+
 // One work-group per tile.  Densities accumulate mass * w in 64-bit fixed
 // point with 2^32 units; the vector scatter (VEC) accumulates coeff * v_j * w
 // one component at a time, in 64-bit fixed point whose unit is chosen from
@@ -452,6 +498,9 @@ k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, 
     const uint32_t total = pre[kRanges];
     constexpr int NC = VEC ? 3 : 1;
     ulonglong2* acc2 = reinterpret_cast<ulonglong2*>(acc);
+    float kw[8], kv[3];   // VEC: the kept first particle
+    uint32_t kcell[4];
+#pragma unroll
     for (int comp = 0; comp < NC; ++comp) {
         for (int c = threadIdx.x; c < T3 / 2; c += NTH) acc2[c] = make_ulonglong2(0ull, 0ull);
         __syncthreads();
@@ -472,9 +521,27 @@ k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, 
             if (VEC) nv = vals[3 * (long)p + comp];
         };
         uint32_t ns = 0;   // slot of the particle after the next
-        if (threadIdx.x < total) fetch(slot(threadIdx.x));
-        if (threadIdx.x + NTH < total) ns = slot(threadIdx.x + NTH);
-        for (uint32_t k = threadIdx.x; k < total; k += NTH) {
+        uint32_t k = threadIdx.x;
+        if constexpr (VEC) {
+            // the thread's first particle: corners and values computed in the
+            // first component's pass and kept for the other two
+            if (comp == 0) {
+                if (k < total) {
+                    const uint32_t p = slot(k);
+                    uint32_t x[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) x[a] = xq[3 * (long)p + a];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) kv[c] = vals[3 * (long)p + c];
+                    corners<T>(x, L, lo, kw, kcell);
+                }
+            }
+            if (k < total) deposit_kept(acc, kw, kcell, amp * kv[comp], e);
+            k += NTH;
+        }
+        if (k < total) fetch(slot(k));
+        if (k + NTH < total) ns = slot(k + NTH);
+        for (; k < total; k += NTH) {
             const uint32_t cur[3] = {nx[0], nx[1], nx[2]};
             const float cv = nv;
             if (k + NTH < total) fetch(ns);
