@@ -90,8 +90,10 @@ def family(sym: str, ng: int):
         return ("scatter_vec", "24P+3r") if targs[1:] == ["true"] else ("scatter", "12P+r")
     if base == "k_gather_tile":
         mode = targs[1] if len(targs) > 1 else ""
-        return {"0": ("gather", "48P+3r"), "1": ("gather", "24P+3r"),
-                "2": ("unkick_vjp", "72P+3r"), "3": ("wgrad", "84P+r")}.get(mode, (None, None))
+        # kick-drift and un-drift gathers also write each moved particle's bin key
+        # and rank (8 bytes) for the next sort
+        return {"0": ("gather", "56P+3r"), "1": ("gather", "24P+3r"),
+                "2": ("unkick_vjp", "72P+3r"), "3": ("wgrad", "92P+r")}.get(mode, (None, None))
     if base in ("k_bin_count", "k_scan_local", "k_scan_bsum", "k_scan_add", "k_index", "k_compact"):
         return "bin", None
     if base.startswith("k_mlp") or base == "k_adam":
@@ -104,8 +106,8 @@ def alg_bytes(rule, grid_y, P, ng):
     c = 8.0 * ng * ng * (ng // 2 + 1)
     return {"rc_per_buf": grid_y * (r + c), "2c_per_buf": grid_y * 2 * c, "3c": 3 * c, "4c": 4 * c,
             "5c": 5 * c, "24P+3r": 24 * P + 3 * r, "12P+r": 12 * P + r,
-            "48P+3r": 48 * P + 3 * r,
-            "72P+3r": 72 * P + 3 * r, "84P+r": 84 * P + r}.get(rule)
+            "56P+3r": 56 * P + 3 * r,
+            "72P+3r": 72 * P + 3 * r, "92P+r": 92 * P + r}.get(rule)
 
 
 def dispatches(db: str, counter: str | None = None):
