@@ -348,6 +348,18 @@ __device__ __forceinline__ unsigned long long to_fixed64(float q) {
     return q < 0.f ? 0ull - u : u;
 }
 
+// LDS slot of tile cell (l0, l1, l2): row-major, with bits 2-3 of l2 swizzled
+// by the row.  A 64-bit LDS word's bank pair depends on l2 alone in row-major
+// order, and the lanes of a wave (particles consecutive in bin order, i.e.
+// nearly in lattice order) share few l2 values across many rows; the swizzle
+// spreads them over four bank groups.  It keeps groups of four consecutive
+// cells together, so the write-out still reads them as two 16-byte words.
+template <int T>
+__device__ __forceinline__ int tile_slot(int l0, int l1, int l2) {
+    constexpr int SW = T / 4 - 1;   // swizzle mask in units of four cells
+    return (l0 * T + l1) * T + (l2 ^ (((l0 ^ l1) & SW) << 2));
+}
+
 // The 8 CIC corners of a particle at x that fall in the tile at lo, added to the
 // tile's accumulator as the fixed-point value of w val 2^e, w the corner's
 // weight (SIGNED: val may be negative).  Node
@@ -380,13 +392,14 @@ __device__ __forceinline__ void deposit(unsigned long long* acc, const uint32_t 
         for (int c1 = 0; c1 < 2; ++c1) {
             if (!in[1][c1]) continue;
             const float w01 = w0 * (c1 ? t[1] : 1.f - t[1]);
-            const int row = (l[0][c0] * T + l[1][c1]) * T;
+
 #pragma unroll
             for (int c2 = 0; c2 < 2; ++c2) {
                 if (!in[2][c2]) continue;
                 const float w = w01 * (c2 ? t[2] : 1.f - t[2]);
                 const float q = ldexpf(w * val, e);
-                atomicAdd(&acc[row + l[2][c2]], SIGNED ? to_fixed64(q) : to_fixed64_nonneg(q));
+                atomicAdd(&acc[tile_slot<T>(l[0][c0], l[1][c1], l[2][c2])],
+                          SIGNED ? to_fixed64(q) : to_fixed64_nonneg(q));
             }
         }
     }
@@ -421,7 +434,7 @@ __device__ __forceinline__ void corners(const uint32_t x[3], const Lattice& L, c
         const float w01 = (c0 ? t[0] : 1.f - t[0]) * (c1 ? t[1] : 1.f - t[1]);
         const float wc = w01 * (c2 ? t[2] : 1.f - t[2]);
         w[c] = in[0][c0] && in[1][c1] && in[2][c2] ? wc : 0.f;
-        const uint32_t cl = (uint32_t)((l[0][c0] * T + l[1][c1]) * T + l[2][c2]) & 0xffffu;
+        const uint32_t cl = (uint32_t)tile_slot<T>(l[0][c0], l[1][c1], l[2][c2]) & 0xffffu;
         if (c & 1) cell2[c >> 1] |= cl << 16;
         else cell2[c >> 1] = cl;
     }
@@ -554,7 +567,8 @@ k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, 
             const int c = 4 * q;
             const int l2 = c % T, l1 = (c / T) % T, l0 = c / (T * T);
             const long g = mesh_row(lo[0] + l0, lo[1] + l1, L.ng) * L.rp + lo[2] + l2;
-            const ulonglong2 a = acc2[2 * q], b = acc2[2 * q + 1];
+            const int sl = tile_slot<T>(l0, l1, l2);   // four consecutive slots
+            const ulonglong2 a = acc2[sl / 2], b = acc2[sl / 2 + 1];
             const unsigned long long v4[4] = {a.x, a.y, b.x, b.y};
             float r4[4];
 #pragma unroll
