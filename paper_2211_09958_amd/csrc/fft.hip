@@ -34,6 +34,9 @@ __device__ __forceinline__ void st_nt(float2* p, float2 v) {
     __builtin_nontemporal_store(v.x, &p->x);
     __builtin_nontemporal_store(v.y, &p->y);
 }
+__device__ __forceinline__ float2 ld_nt(const float2* p) {
+    return make_float2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
+}
 
 // Lanes-per-transform and values-per-lane choices per transform length.
 template <int H>
@@ -260,11 +263,28 @@ k_grad_z(const float2* __restrict__ src, float2* __restrict__ dst, long dstStrid
 }
 
 // k_grad_z for the largest transforms, whose register footprint allows one
-// work-group per CU: a persistent loop over tiles in which the column of the
-// next tile is loaded while the current one is transformed, so that the loads
-// overlap the transforms instead of alternating with them.  Work-group b takes
-// tiles lw, lw + nwg, ... with lw its XCD-contiguous index, so the work-groups
-// of one XCD work on neighbouring column blocks at any time.
+// work-group per CU: a persistent loop over tiles in which the column and the
+// radial multipliers of the next tile are loaded while the current one is
+// transformed, so that the loads overlap the transforms instead of alternating
+// with them.  Work-group b takes tiles lw, lw + nwg, ... with lw its
+// XCD-contiguous index, so the work-groups of one XCD work on neighbouring
+// column blocks at any time.
+//
+// Vector-memory operations of a wave complete in issue order, so a wait for a
+// load also waits for every load and store issued before it.  The loop is
+// arranged so that the only such wait is the one at the top of a tile, for the
+// prefetched column, which the stores of the previous tile (issued after it)
+// do not delay: the stage twiddles are read from an LDS copy, the radial
+// multipliers come with the prefetch, and the prefetch is unconditional (the
+// last tile reloads itself) so that every path into the loop header leaves the
+// same operations in flight.
+//
+// The radial multiplier is a table lookup at |n|^2, which scatters a tile's
+// lookups over the whole table (one cache line per lookup, nearly); modes n0
+// and -n0 share it, so each lane looks up only |n0| = q <= H/2 and the values
+// reach the lanes of both modes through LDS (rq), halving the lookups.  The
+// column itself streams through once: non-temporal loads and stores keep it
+// from evicting the table from L2.
 template <int H>
 __global__ void __launch_bounds__(Cfg<H>::T * Cfg<H>::W)
 k_grad_z_pipe(const float2* __restrict__ src, float2* __restrict__ dst, long dstStride, int cs,
@@ -272,11 +292,20 @@ k_grad_z_pipe(const float2* __restrict__ src, float2* __restrict__ dst, long dst
               int ntw, const float2* __restrict__ st) {
     constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::W, n = H;
     constexpr int LS = lds_slots(H) * W;
+    // radial lookups per lane: q = j + e T for e < EQ - 1, and q = H/2
+    constexpr int EQ = (H / 2) / T + 1;
     static_assert(T % 16 == 0, "rows j + e T must share their in-block index");
-    // lds: the transforms' exchange buffer; keep: radial * delta_k of the
-    // column (held in LDS rather than registers, which hold the next column)
-    __shared__ float2 lds[2 * LS];
+    static_assert((H / 2) % T == 0, "q = j + e T covers 0 .. H/2 - 1");
+    // lds: the transforms' exchange buffer; keep (unpadded: each lane reads
+    // back only its own slots): radial * delta_k of the column (held in LDS
+    // rather than registers, which hold the next column); tab: the H-point
+    // part of the stage-twiddle table (H - 1 entries); rq: the tile's radial
+    // multipliers by q = |n0|
+    __shared__ float2 lds[LS + H * W + H];
+    __shared__ float rq[(H / 2 + 1) * W];
     float2* keep = lds + LS;
+    float2* tab = keep + H * W;
+    for (int i = threadIdx.x; i < H - 1; i += T * W) tab[i] = st[H + i];
     const int c = threadIdx.x % W, j = threadIdx.x / W;
     const int nwg = (int)gridDim.x;
     const int lw = (int)xcd_block(blockIdx.x, gridDim.x);
@@ -293,42 +322,59 @@ k_grad_z_pipe(const float2* __restrict__ src, float2* __restrict__ dst, long dst
     auto at = [](const float2* base, long e_off, uint32_t lane) -> const float2* {
         return reinterpret_cast<const float2*>(reinterpret_cast<const char*>(base + e_off) + lane);
     };
+    // table index of this lane's e-th lookup for a tile (0 off the stored
+    // half, whose multipliers are replaced by zero)
+    auto rad_index = [&](int tile, int e) -> int {
+        const int n1 = signed_freq(tile / ncb, n), k2 = (tile % ncb) * W + c;
+        const int q = e < EQ - 1 ? j + e * T : n / 2;
+        return k2 <= n / 2 ? q * q + n1 * n1 + k2 * k2 : 0;
+    };
+    if (lw >= ntiles) return;
     float2 nx[E];
-    if (lw < ntiles) {
+    float nr[EQ];
+    {
         const uint32_t lo = lane_off(lw);
 #pragma unroll
-        for (int e = 0; e < E; ++e) nx[e] = *at(src, e * estride, lo);
+        for (int e = 0; e < EQ; ++e) nr[e] = radial[rad_index(lw, e)];
+#pragma unroll
+        for (int e = 0; e < E; ++e) nx[e] = ld_nt(at(src, e * estride, lo));
     }
+    // no loads in flight on entry to the loop (see above)
+    __builtin_amdgcn_s_waitcnt(0);
     for (int tile = lw; tile < ntiles; tile += nwg) {
-        const int i1 = tile / ncb, k2 = (tile % ncb) * W + c;
+        const bool in_half = (tile % ncb) * W + c <= n / 2;
         const uint32_t lo = lane_off(tile);
         float2 v[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = nx[e];
-        if (tile + nwg < ntiles) {
-            const uint32_t ln = lane_off(tile + nwg);
+        // rq is free: the previous tile read it before its last transforms
 #pragma unroll
-            for (int e = 0; e < E; ++e) nx[e] = *at(src, e * estride, ln);
+        for (int e = 0; e < EQ - 1; ++e) rq[(j + e * T) * W + c] = in_half ? nr[e] : 0.f;
+        if (j == 0) rq[(n / 2) * W + c] = in_half ? nr[EQ - 1] : 0.f;
+        {
+            const int next = tile + nwg < ntiles ? tile + nwg : tile;
+            const uint32_t ln = lane_off(next);
+#pragma unroll
+            for (int e = 0; e < EQ; ++e) nr[e] = radial[rad_index(next, e)];
+#pragma unroll
+            for (int e = 0; e < E; ++e) nx[e] = ld_nt(at(src, e * estride, ln));
         }
-        fft_lds<H, E, -1>(v, lds, W, c, j, st);
+        fft_lds_tab<H, E, -1>(v, lds, W, c, j, tab);
         __syncthreads();
-        const int n1 = signed_freq(i1, n);
-        const bool in_half = k2 <= n / 2;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int p = j + e * T;
-            const int n0 = signed_freq(p, n);
-            const float rad = in_half ? radial[n0 * n0 + n1 * n1 + k2 * k2] : 0.f;
+            const float rad = rq[(p <= n / 2 ? p : n - p) * W + c];
             const float2 x = lds[lpad(p) * W + c];
             v[e] = make_float2(rad * x.x, rad * x.y);
-            keep[lpad(p) * W + c] = v[e];
+            keep[p * W + c] = v[e];
         }
         __syncthreads();
-        fft_lds<H, E, 1>(v, lds, W, c, j, st);
+        fft_lds_tab<H, E, 1>(v, lds, W, c, j, tab);
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < E; ++e)
-            *const_cast<float2*>(at(dst + dstStride, e * estride, lo)) = lds[lpad(j + e * T) * W + c];
+            st_nt(const_cast<float2*>(at(dst + dstStride, e * estride, lo)), lds[lpad(j + e * T) * W + c]);
         // F~_0 multiplier i n0 (zero on the Nyquist plane) on the kept column;
         // each lane reads back only the slots it wrote itself
 #pragma unroll
@@ -336,15 +382,15 @@ k_grad_z_pipe(const float2* __restrict__ src, float2* __restrict__ dst, long dst
             const int p = j + e * T;
             const int n0 = signed_freq(p, n);
             const float f0 = n0 == -n / 2 ? 0.f : (float)n0;
-            const float2 d = keep[lpad(p) * W + c];
+            const float2 d = keep[p * W + c];
             v[e] = make_float2(-d.y * f0, d.x * f0);
         }
         __syncthreads();
-        fft_lds<H, E, 1>(v, lds, W, c, j, st);
+        fft_lds_tab<H, E, 1>(v, lds, W, c, j, tab);
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < E; ++e)
-            *const_cast<float2*>(at(dst, e * estride, lo)) = lds[lpad(j + e * T) * W + c];
+            st_nt(const_cast<float2*>(at(dst, e * estride, lo)), lds[lpad(j + e * T) * W + c]);
         __syncthreads();   // the next tile's first transform reuses lds
     }
 }
@@ -457,10 +503,12 @@ k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
 }
 
 // k_grad_adj_z (without the filter cotangent) for the largest transforms, as a
-// persistent loop like k_grad_z_pipe: the G_0 column of the next tile is loaded
-// during the current tile's transforms, the current tile's G_1 and G_2 columns
-// are loaded before its first transform, and the sum
-// n0 G_0 + n1 G_1 + n2 G_2 of the forward transforms is kept in LDS.
+// persistent loop over tiles like k_grad_z_pipe: the tile's radial lookups and
+// its G_0, G_1 and G_2 columns are loaded at the top of the tile, and the sum
+// n0 G_0 + n1 G_1 + n2 G_2 of the forward transforms is kept in LDS.  As in
+// k_grad_z_pipe, each lane looks up the radial multipliers of |n0| <= H/2 only
+// and shares them through LDS, and the columns stream with non-temporal loads
+// and stores.
 template <int H>
 __global__ void __launch_bounds__(Cfg<H>::T * Cfg<H>::W)
 k_grad_adj_z_pipe(const float2* __restrict__ src, long srcStride, float2* dst, int cs, int ncb,
@@ -468,13 +516,16 @@ k_grad_adj_z_pipe(const float2* __restrict__ src, long srcStride, float2* dst, i
                   int ntw, const float2* __restrict__ st) {
     constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::W, n = H;
     constexpr int LS = lds_slots(H) * W;
+    constexpr int EQ = (H / 2) / T + 1;   // radial lookups per lane (k_grad_z_pipe)
     static_assert(T % 16 == 0, "rows j + e T must share their in-block index");
-    __shared__ float2 lds[2 * LS];
-    __shared__ float2 twl[H];   // this length's stage twiddles
+    static_assert((H / 2) % T == 0, "q = j + e T covers 0 .. H/2 - 1");
+    // exchange buffer | keep (unpadded, own slots only) | stage twiddles
+    __shared__ float2 lds[LS + H * W + H];
+    __shared__ float rq[(H / 2 + 1) * W];
     float2* keep = lds + LS;
+    float2* twl = keep + H * W;
     const int c = threadIdx.x % W, j = threadIdx.x / W;
-    for (int i = threadIdx.x; i < H; i += T * W) twl[i] = st[H + i];
-    __syncthreads();
+    for (int i = threadIdx.x; i < H - 1; i += T * W) twl[i] = st[H + i];
     const int nwg = (int)gridDim.x;
     const int lw = (int)xcd_block(blockIdx.x, gridDim.x);
     // wave-uniform row-block part e T n cs and a 32-bit lane part (k_grad_z_pipe)
@@ -495,14 +546,27 @@ k_grad_adj_z_pipe(const float2* __restrict__ src, long srcStride, float2* dst, i
         const bool in_half = k2 <= n / 2;
         const float f1 = n1 == -n / 2 ? 0.f : (float)n1;
         const float f2 = k2 == n / 2 ? 0.f : (float)k2;
+        float nr[EQ];
+#pragma unroll
+        for (int e = 0; e < EQ; ++e) {
+            const int q = e < EQ - 1 ? j + e * T : n / 2;
+            nr[e] = radial[in_half ? q * q + n1 * n1 + k2 * k2 : 0];
+        }
         float2 v[E], y1[E], y2[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = *at(src, e * estride, lo);
+        for (int e = 0; e < E; ++e) v[e] = ld_nt(at(src, e * estride, lo));
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            y1[e] = *at(g1, e * estride, lo);
-            y2[e] = *at(g2, e * estride, lo);
+            y1[e] = ld_nt(at(g1, e * estride, lo));
+            y2[e] = ld_nt(at(g2, e * estride, lo));
         }
+        // rq is free: the previous tile read it before its last transform
+#pragma unroll
+        for (int e = 0; e < EQ - 1; ++e) rq[(j + e * T) * W + c] = in_half ? nr[e] : 0.f;
+        // keeps the H/2 lookup here, issued with the others: sunk into the
+        // branch below, its wait would also wait for the columns
+        __asm__ volatile("" ::"v"(nr[EQ - 1]));
+        if (j == 0) rq[(n / 2) * W + c] = in_half ? nr[EQ - 1] : 0.f;
         // forward FFT of G_0, kept as n0 G_0 (zero on its Nyquist plane)
         fft_lds_tab<H, E, -1>(v, lds, W, c, j, twl);
         __syncthreads();
@@ -512,7 +576,7 @@ k_grad_adj_z_pipe(const float2* __restrict__ src, long srcStride, float2* dst, i
             const int n0 = signed_freq(p, n);
             const float f0 = n0 == -n / 2 ? 0.f : (float)n0;
             const float2 g = lds[lpad(p) * W + c];
-            keep[lpad(p) * W + c] = make_float2(f0 * g.x, f0 * g.y);
+            keep[p * W + c] = make_float2(f0 * g.x, f0 * g.y);
         }
         // forward FFT of n1 G_1 + n2 G_2, added to the kept column
 #pragma unroll
@@ -526,9 +590,8 @@ k_grad_adj_z_pipe(const float2* __restrict__ src, long srcStride, float2* dst, i
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int p = j + e * T;
-            const int n0 = signed_freq(p, n);
-            const float rad = in_half ? radial[n0 * n0 + n1 * n1 + k2 * k2] : 0.f;
-            const float2 g = lds[lpad(p) * W + c], k = keep[lpad(p) * W + c];
+            const float rad = rq[(p <= n / 2 ? p : n - p) * W + c];
+            const float2 g = lds[lpad(p) * W + c], k = keep[p * W + c];
             const float2 a = make_float2(k.x + g.x, k.y + g.y);
             v[e] = make_float2(rad * a.y, -rad * a.x);
         }
@@ -537,7 +600,7 @@ k_grad_adj_z_pipe(const float2* __restrict__ src, long srcStride, float2* dst, i
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < E; ++e)
-            *const_cast<float2*>(at(dst, e * estride, lo)) = lds[lpad(j + e * T) * W + c];
+            st_nt(const_cast<float2*>(at(dst, e * estride, lo)), lds[lpad(j + e * T) * W + c]);
         __syncthreads();   // the next tile's first transform reuses lds
     }
 }
