@@ -70,7 +70,7 @@ k_fft_x_r2c(float2* __restrict__ buf, int cs, long nrows, long bufStride,
     const int twN = ntw / N;
     float2 v[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = valid ? rowp[j + e * T] : make_float2(0.f, 0.f);
+    for (int e = 0; e < E; ++e) v[e] = valid ? ld_nt(&rowp[j + e * T]) : make_float2(0.f, 0.f);
     float2* L = lds + r * LS;
     fft_lds<H, E, -1>(v, L, 1, 0, j, st);
     __syncthreads();
@@ -112,7 +112,7 @@ k_fft_x_c2r(float2* __restrict__ buf, int cs, long nrows, long bufStride, int km
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = j + e * T;
-        float2 x = valid ? rowp[k] : make_float2(0.f, 0.f);
+        float2 x = valid ? ld_nt(&rowp[k]) : make_float2(0.f, 0.f);
         if (kmul) x = make_float2(-(float)k * x.y, (float)k * x.x);
         L[lpad(k)] = x;
     }
