@@ -68,9 +68,14 @@ k_fft_x_r2c(float2* __restrict__ buf, int cs, long nrows, long bufStride,
     const bool valid = row < nrows;
     float2* rowp = buf + blockIdx.y * bufStride + (valid ? row : 0) * cs;
     const int twN = ntw / N;
+    // rowp points at row 0 for rows past the end, so every load is in bounds
+    // and none sits in a branch (which would make each wait for its data)
     float2 v[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = valid ? ld_nt(&rowp[j + e * T]) : make_float2(0.f, 0.f);
+    for (int e = 0; e < E; ++e) {
+        v[e] = ld_nt(&rowp[j + e * T]);
+        if (!valid) v[e] = make_float2(0.f, 0.f);
+    }
     float2* L = lds + r * LS;
     fft_lds<H, E, -1>(v, L, 1, 0, j, st);
     __syncthreads();
@@ -109,21 +114,32 @@ k_fft_x_c2r(float2* __restrict__ buf, int cs, long nrows, long bufStride, int km
     const int twN = ntw / N;
     float2* L = lds + r * LS;
     const bool kmul = (int)blockIdx.y == kmul_buf;
+    // rowp points at row 0 for rows past the end, so every load is in bounds
+    // and none sits in a branch (which would make each wait for its data)
+    float2 x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = ld_nt(&rowp[j + e * T]);
+    const float2 xh = ld_nt(&rowp[H]);
+    // the pre-twiddles, loaded with the row (a load after the barrier below
+    // would be waited for there)
+    float2 twk[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) twk[e] = tw[(j + e * T) * twN];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = j + e * T;
-        float2 x = valid ? ld_nt(&rowp[k]) : make_float2(0.f, 0.f);
-        if (kmul) x = make_float2(-(float)k * x.y, (float)k * x.x);
-        L[lpad(k)] = x;
+        float2 y = valid ? x[e] : make_float2(0.f, 0.f);
+        if (kmul) y = make_float2(-(float)k * y.y, (float)k * y.x);
+        L[lpad(k)] = y;
     }
-    if (j == 0) L[lpad(H)] = (valid && !kmul) ? rowp[H] : make_float2(0.f, 0.f);
+    if (j == 0) L[lpad(H)] = (valid && !kmul) ? xh : make_float2(0.f, 0.f);
     __syncthreads();
     float2 v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = j + e * T;
         float2 xk = L[lpad(k)], xc = cconj(L[lpad(H - k)]);
-        float2 A = cadd(xk, xc), B = cmulc(csub(xk, xc), tw[k * twN]);
+        float2 A = cadd(xk, xc), B = cmulc(csub(xk, xc), twk[e]);
         v[e] = cadd(A, cmul_i<1>(B));
     }
     __syncthreads();
