@@ -297,6 +297,35 @@ k_compact(uint32_t* __restrict__ ord, long P, Records rec) {
     ord[k] = (uint32_t)k;
 }
 
+// Words per particle of the record sets the sorts move: positions, momenta,
+// ids, then (with the cotangents) xi and pi.
+constexpr int kSortWords[5] = {3, 3, 1, 3, 3};
+
+// k_compact for the first N arrays of that layout: with the word counts fixed
+// at compile time, every gather load of a particle is issued before the first
+// wait (the branches on the run-time layout make k_compact wait once per array).
+template <int N>
+__global__ void __launch_bounds__(kBlock)
+k_compact_sorted(uint32_t* __restrict__ ord, long P, Records rec) {
+    const long k = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (k >= P) return;
+    const long i = ord[k];
+    uint32_t buf[N][3];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        const uint32_t* src = rec.src[a] + i * kSortWords[a];
+#pragma unroll
+        for (int j = 0; j < kSortWords[a]; ++j) buf[a][j] = src[j];
+    }
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        uint32_t* dst = rec.dst[a] + k * kSortWords[a];
+#pragma unroll
+        for (int j = 0; j < kSortWords[a]; ++j) dst[j] = buf[a][j];
+    }
+    ord[k] = (uint32_t)k;
+}
+
 // ------------------------------------------------------------- scatter
 
 // The 20 particle ranges a tile work-group visits: its own 8 classes, then for
@@ -638,6 +667,9 @@ constexpr int gather_threads(int mode) { return mode == kWgrad ? kBlock : 4 * kB
 
 // A particle's inputs, loaded before any of its outputs is stored (a load after
 // a store to an array that may alias it would wait a full memory round trip).
+// Records are indexed in 64 bits (3 * (size_t)p + a): with a 32-bit index the
+// compiler cannot rule out a wrap between a record's words and moves each word
+// in an access of its own.
 struct GatherRec {
     uint32_t x[3];
     int32_t pm[3];
@@ -647,28 +679,28 @@ struct GatherRec {
 template <int MODE>
 __device__ __forceinline__ void gather_load(const GatherArgs& A, uint32_t p, GatherRec& r) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) r.x[a] = A.xq[3 * p + a];
+    for (int a = 0; a < 3; ++a) r.x[a] = A.xq[3 * (size_t)p + a];
     if constexpr (MODE == kKickDrift) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) r.pm[a] = A.pq[3 * p + a];
+        for (int a = 0; a < 3; ++a) r.pm[a] = A.pq[3 * (size_t)p + a];
     } else if constexpr (MODE == kUnkickVjp) {
         if (A.pq) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) r.pm[a] = A.pq[3 * p + a];
+            for (int a = 0; a < 3; ++a) r.pm[a] = A.pq[3 * (size_t)p + a];
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            r.pin[a] = A.pi_in[3 * p + a];
-            r.xin[a] = A.xi[3 * p + a];
+            r.pin[a] = A.pi_in[3 * (size_t)p + a];
+            r.xin[a] = A.xi[3 * (size_t)p + a];
         }
     } else if constexpr (MODE == kWgrad) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) r.xin[a] = A.xi[3 * p + a];
+        for (int a = 0; a < 3; ++a) r.xin[a] = A.xi[3 * (size_t)p + a];
         if (A.flag == 1) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                r.pm[a] = A.pq[3 * p + a];
-                r.pin[a] = A.pi[3 * p + a];
+                r.pm[a] = A.pq[3 * (size_t)p + a];
+                r.pin[a] = A.pi[3 * (size_t)p + a];
             }
         }
     }
@@ -725,20 +757,22 @@ __device__ __forceinline__ double gather_apply(const GatherArgs& A, const Lattic
             bad = bad || !(fabsf(q) < 2.0e9f) || sum != (long long)m[a];
         }
         if (bad && A.ovf) atomicOr(A.ovf, 1u);
+        // each array's three words stored together (one access each)
         if (A.ck_x) {
             const long q = A.id[p];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                A.ck_x[3 * q + a] = r.x[a];
-                A.ck_p[3 * q + a] = m[a];
-            }
+            for (int a = 0; a < 3; ++a) A.ck_x[3 * q + a] = r.x[a];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) A.ck_p[3 * q + a] = m[a];
         }
         uint32_t xn[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            xn[a] = r.x[a] + drift_units(A.drift, m[a], L);
-            A.pq[3 * p + a] = m[a];
-            if (A.flag) A.xq[3 * p + a] = xn[a];
+        for (int a = 0; a < 3; ++a) xn[a] = r.x[a] + drift_units(A.drift, m[a], L);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) A.pq[3 * (size_t)p + a] = m[a];
+        if (A.flag) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) A.xq[3 * (size_t)p + a] = xn[a];
         }
         if (A.flag && A.count) {
             const uint32_t key = bin_key(xn, L, A.btile);
@@ -753,11 +787,11 @@ __device__ __forceinline__ double gather_apply(const GatherArgs& A, const Lattic
     } else if constexpr (MODE == kUnkickVjp) {
         if (A.pq) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) A.pq[3 * p + a] = r.pm[a] - kick_units(A.coeff, F[a], L);
+            for (int a = 0; a < 3; ++a) A.pq[3 * (size_t)p + a] = r.pm[a] - kick_units(A.coeff, F[a], L);
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a)
-            A.xi[3 * p + a] =
+            A.xi[3 * (size_t)p + a] =
                 r.xin[a] + A.coeff * (r.pin[0] * G[0][a] + r.pin[1] * G[1][a] + r.pin[2] * G[2][a]);
         acc = (double)r.pin[0] * F[0] + (double)r.pin[1] * F[1] + (double)r.pin[2] * F[2];
     } else {   // kWgrad
@@ -765,7 +799,7 @@ __device__ __forceinline__ double gather_apply(const GatherArgs& A, const Lattic
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             xv[a] = r.xin[a] + A.coeff * G[0][a];
-            A.xi[3 * p + a] = xv[a];
+            A.xi[3 * (size_t)p + a] = xv[a];
         }
         if (A.flag == 1) {
             uint32_t xn[3];
@@ -773,9 +807,9 @@ __device__ __forceinline__ double gather_apply(const GatherArgs& A, const Lattic
             for (int a = 0; a < 3; ++a) {
                 const int32_t m = r.pm[a];
                 acc += (double)xv[a] * ((double)m * L.mom_unit);
-                A.pi[3 * p + a] = r.pin[a] + A.drift * xv[a];
+                A.pi[3 * (size_t)p + a] = r.pin[a] + A.drift * xv[a];
                 xn[a] = r.x[a] - drift_units(A.drift, m, L);
-                A.xq[3 * p + a] = xn[a];
+                A.xq[3 * (size_t)p + a] = xn[a];
             }
             if (A.count) {
                 const uint32_t key = bin_key(xn, L, A.btile);
@@ -1331,8 +1365,15 @@ void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, bool counted, hip
 }
 
 void launch_compact(Bins& b, const Records& rec, long P, hipStream_t s) {
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       b.ord, P, rec);
+    const dim3 grid((unsigned)((P + kBlock - 1) / kBlock));
+    bool sorted_layout = rec.n == 3 || rec.n == 5;
+    for (int a = 0; a < rec.n && sorted_layout; ++a) sorted_layout = rec.words[a] == kSortWords[a];
+    if (sorted_layout && rec.n == 3)
+        hipLaunchKernelGGL(k_compact_sorted<3>, grid, dim3(kBlock), 0, s, b.ord, P, rec);
+    else if (sorted_layout)
+        hipLaunchKernelGGL(k_compact_sorted<5>, grid, dim3(kBlock), 0, s, b.ord, P, rec);
+    else
+        hipLaunchKernelGGL(k_compact, grid, dim3(kBlock), 0, s, b.ord, P, rec);
 }
 
 template <bool VEC>
