@@ -183,38 +183,43 @@ __device__ __forceinline__ int signed_freq(int p, int n) { return p < n / 2 ? p 
 // Inverse axis-1 pass that splits G into the two spectra it feeds: out_g =
 // IFFT_1(G) (F~_2 = i k2 times it, applied by the last-axis C2R) and, in place,
 // F~_1 = IFFT_1(i n1 G) (zero on the Nyquist plane of axis 1).  The column is
-// loaded twice (the second load mostly from L2) so that only one transform's
-// values are held in registers at a time.
+// loaded once and held in registers for the second transform (a reload misses
+// L2: the other work-groups stream several times its size through it in
+// between); the stage twiddles come from an LDS copy, which leaves the
+// registers for it.
 template <int H>
 __global__ void __launch_bounds__(Cfg<H>::T * Cfg<H>::W, Cfg<H>::MINW)
 k_fft_y_split(float2* __restrict__ g, float2* __restrict__ out_g, int cs, int ncb,
               const float2* __restrict__ tw, int ntw, const float2* __restrict__ st) {
     constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::W;
-    __shared__ float2 lds[lds_slots(H) * W];
+    // exchange buffer | the H-point part of the stage-twiddle table (H - 1 entries)
+    __shared__ float2 lds[lds_slots(H) * W + H];
+    float2* tab = lds + lds_slots(H) * W;
+    // read first in the second stage, after the first stage's barrier
+    for (int i = threadIdx.x; i < H - 1; i += T * W) tab[i] = st[H + i];
     const int c = threadIdx.x % W, j = threadIdx.x / W;
     const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
     const int a = tile / ncb, cb = tile % ncb;   // a: axis-0 index
     const int k2 = cb * W + c;
     auto off = [&](int p) -> long { return mesh_row(a, p, H) * cs + k2; };
-    float2 v[E];
+    float2 x[E], v[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = g[off(j + e * T)];
-    fft_lds<H, E, 1>(v, lds, W, c, j, st);
+    for (int e = 0; e < E; ++e) {
+        x[e] = g[off(j + e * T)];
+        v[e] = x[e];
+    }
+    fft_lds_tab<H, E, 1>(v, lds, W, c, j, tab);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) out_g[off(j + e * T)] = lds[lpad(j + e * T) * W + c];
-    // compiler-only barrier: the reload must not be hoisted above the first
-    // transform, where its registers would be live alongside it
-    __asm__ volatile("" ::: "memory");
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int p = j + e * T;
         const float f1 = p == H / 2 ? 0.f : (float)signed_freq(p, H);
-        const float2 x = g[off(p)];
-        v[e] = make_float2(-f1 * x.y, f1 * x.x);
+        v[e] = make_float2(-f1 * x[e].y, f1 * x[e].x);
     }
     __syncthreads();   // every lane has read the first transform's output
-    fft_lds<H, E, 1>(v, lds, W, c, j, st);
+    fft_lds_tab<H, E, 1>(v, lds, W, c, j, tab);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) g[off(j + e * T)] = lds[lpad(j + e * T) * W + c];
