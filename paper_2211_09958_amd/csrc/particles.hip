@@ -550,10 +550,12 @@ k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, 
         // particle's storage slot is loaded two iterations ahead and its record
         // one iteration ahead, so neither load is waited for before the atomics
         // of the particle in hand are issued
+        // a thread looks up increasing indices (kk < total), so the range
+        // search resumes where the previous lookup stopped
+        int rcur = 0;
         auto slot = [&](uint32_t kk) {
-            int r = 0;
-            while (pre[r + 1] <= kk) ++r;
-            return ord[rs[r] + (kk - pre[r])];
+            while (pre[rcur + 1] <= kk) ++rcur;
+            return ord[rs[rcur] + (kk - pre[rcur])];
         };
         uint32_t nx[3] = {0u, 0u, 0u};
         float nv = 0.f;
