@@ -724,7 +724,11 @@ __device__ __forceinline__ double gather_apply(const GatherArgs& A, const Lattic
     int b[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) b[a] = (ii[a] - lo[a]) & mask;   // in [0, T)
-    float F[NM] = {0.f}, G[NM][3] = {{0.f}};
+    // G[a]: the gradient of the interpolated mesh along axis a; for the
+    // transposed kick only its contraction with the momentum cotangent is used,
+    // Sum_m pin_m dF_m/dx_a = Sum_corners dw/dx_a (Sum_m pin_m f_m), which is
+    // formed corner by corner (three accumulators instead of nine)
+    float F[NM] = {0.f}, G[3] = {0.f, 0.f, 0.f};
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const int c0 = c >> 2, c1 = (c >> 1) & 1, c2 = c & 1;
@@ -734,15 +738,18 @@ __device__ __forceinline__ double gather_apply(const GatherArgs& A, const Lattic
         const float a2 = c2 ? t[2] : 1.f - t[2];
         const float w = __fmul_rn(__fmul_rn(a0, a1), a2);
         const float d0 = c0 ? ic : -ic, d1 = c1 ? ic : -ic, d2 = c2 ? ic : -ic;
+        float g = 0.f;   // kWgrad: f; kUnkickVjp: Sum_m pin_m f_m
 #pragma unroll
         for (int m = 0; m < NM; ++m) {
             const float f = mf[m * TH3 + li];
             if constexpr (MODE != kWgrad) F[m] = __fmaf_rn(w, f, F[m]);
-            if constexpr (MODE == kUnkickVjp || MODE == kWgrad) {
-                G[m][0] += d0 * a1 * a2 * f;
-                G[m][1] += a0 * d1 * a2 * f;
-                G[m][2] += a0 * a1 * d2 * f;
-            }
+            if constexpr (MODE == kUnkickVjp) g += r.pin[m] * f;
+            if constexpr (MODE == kWgrad) g = f;
+        }
+        if constexpr (MODE == kUnkickVjp || MODE == kWgrad) {
+            G[0] += d0 * a1 * a2 * g;
+            G[1] += a0 * d1 * a2 * g;
+            G[2] += a0 * a1 * d2 * g;
         }
     }
     double acc = 0.0;
@@ -792,15 +799,13 @@ __device__ __forceinline__ double gather_apply(const GatherArgs& A, const Lattic
             for (int a = 0; a < 3; ++a) A.pq[3 * (size_t)p + a] = r.pm[a] - kick_units(A.coeff, F[a], L);
         }
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-            A.xi[3 * (size_t)p + a] =
-                r.xin[a] + A.coeff * (r.pin[0] * G[0][a] + r.pin[1] * G[1][a] + r.pin[2] * G[2][a]);
+        for (int a = 0; a < 3; ++a) A.xi[3 * (size_t)p + a] = r.xin[a] + A.coeff * G[a];
         acc = (double)r.pin[0] * F[0] + (double)r.pin[1] * F[1] + (double)r.pin[2] * F[2];
     } else {   // kWgrad
         float xv[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            xv[a] = r.xin[a] + A.coeff * G[0][a];
+            xv[a] = r.xin[a] + A.coeff * G[a];
             A.xi[3 * (size_t)p + a] = xv[a];
         }
         if (A.flag == 1) {
