@@ -237,7 +237,12 @@ k_grad_z(const float2* __restrict__ src, float2* __restrict__ dst, long dstStrid
          int ncb, const float* __restrict__ radial, const float2* __restrict__ tw, int ntw,
             const float2* __restrict__ st) {
     constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::W, n = H;
-    __shared__ float2 lds[lds_slots(H) * W];
+    // exchange buffer | the H-point part of the stage-twiddle table (read from
+    // LDS rather than hoisted into registers, which hold the column)
+    __shared__ float2 lds[lds_slots(H) * W + H];
+    float2* tab = lds + lds_slots(H) * W;
+    // read first in the second stage, after the first stage's barrier
+    for (int i = threadIdx.x; i < H - 1; i += T * W) tab[i] = st[H + i];
     const int c = threadIdx.x % W, j = threadIdx.x / W;
     const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
     const int i1 = tile / ncb, cb = tile % ncb;
@@ -247,7 +252,7 @@ k_grad_z(const float2* __restrict__ src, float2* __restrict__ dst, long dstStrid
     float2 v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = src[off(j + e * T)];
-    fft_lds<H, E, -1>(v, lds, W, c, j, st);
+    fft_lds_tab<H, E, -1>(v, lds, W, c, j, tab);
     __syncthreads();
     const int n1 = signed_freq(i1, n);
     const bool in_half = k2 <= n / 2;
@@ -263,7 +268,7 @@ k_grad_z(const float2* __restrict__ src, float2* __restrict__ dst, long dstStrid
         v[e] = d[e];
     }
     __syncthreads();
-    fft_lds<H, E, 1>(v, lds, W, c, j, st);
+    fft_lds_tab<H, E, 1>(v, lds, W, c, j, tab);
     __syncthreads();
     {
         float2* og = dst + dstStride;
@@ -277,7 +282,7 @@ k_grad_z(const float2* __restrict__ src, float2* __restrict__ dst, long dstStrid
         v[e] = make_float2(-d[e].y * f0, d[e].x * f0);
     }
     __syncthreads();
-    fft_lds<H, E, 1>(v, lds, W, c, j, st);
+    fft_lds_tab<H, E, 1>(v, lds, W, c, j, tab);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) dst[off(j + e * T)] = lds[lpad(j + e * T) * W + c];
@@ -427,7 +432,12 @@ k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
              float* __restrict__ fbar, float fscale, const float2* __restrict__ tw, int ntw,
             const float2* __restrict__ st) {
     constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::W, n = H;
-    __shared__ float2 lds[lds_slots(H) * W];
+    // exchange buffer | the H-point part of the stage-twiddle table (read from
+    // LDS rather than hoisted into registers, which hold the column)
+    __shared__ float2 lds[lds_slots(H) * W + H];
+    float2* tab = lds + lds_slots(H) * W;
+    // read first in the second stage, after the first stage's barrier
+    for (int i = threadIdx.x; i < H - 1; i += T * W) tab[i] = st[H + i];
     const int c = threadIdx.x % W, j = threadIdx.x / W;
     const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
     const int i1 = tile / ncb, cb = tile % ncb;
@@ -442,7 +452,7 @@ k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
     // forward FFT of G_0, kept as n0 G_0 (zero on its Nyquist plane)
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = src[off(j + e * T)];
-    fft_lds<H, E, -1>(v, lds, W, c, j, st);
+    fft_lds_tab<H, E, -1>(v, lds, W, c, j, tab);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -463,7 +473,7 @@ k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
         }
     }
     __syncthreads();
-    fft_lds<H, E, -1>(v, lds, W, c, j, st);
+    fft_lds_tab<H, E, -1>(v, lds, W, c, j, tab);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -476,7 +486,7 @@ k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = dens[off(j + e * T)];
         __syncthreads();
-        fft_lds<H, E, -1>(v, lds, W, c, j, st);
+        fft_lds_tab<H, E, -1>(v, lds, W, c, j, tab);
         __syncthreads();
         // each lane turns its own elements' dens_k into their contribution (in
         // the same LDS slot), then the modes n0 and -n0, which share |n|^2, are
@@ -517,7 +527,7 @@ k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
         v[e] = make_float2(rad * a[e].y, -rad * a[e].x);
     }
     __syncthreads();
-    fft_lds<H, E, 1>(v, lds, W, c, j, st);
+    fft_lds_tab<H, E, 1>(v, lds, W, c, j, tab);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) dst[off(j + e * T)] = lds[lpad(j + e * T) * W + c];
