@@ -122,8 +122,11 @@ void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, bool counted, hip
 // Zeroes the bin counts ahead of a gather that counts the particles it moves.
 void launch_bin_zero(Bins& b, hipStream_t s);
 // Moves every record array from src to dst in the order b.ord and resets b.ord
-// to the identity (each bin then a contiguous range of the records).
-void launch_compact(Bins& b, const Records& rec, long P, hipStream_t s);
+// to the identity (each bin then a contiguous range of the records).  The
+// records must be the sorts' set: positions (3 words), momenta (3), ids (1),
+// optionally followed by xi (3) and pi (3); returns false, launching nothing,
+// for any other layout.
+bool launch_compact(Bins& b, const Records& rec, long P, hipStream_t s);
 // Density delta = rho - 1 (particle mass (ng/np)^3) into a real mesh with pitch
 // L.rp; every cell written once (no pre-zeroing), deterministic.
 void launch_scatter_density(const uint32_t* xq, const Lattice& L, const Bins& b, float* mesh,

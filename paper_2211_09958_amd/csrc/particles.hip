@@ -264,46 +264,16 @@ k_index(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ ranks,
     if (i < P) ord[offsets[keys[i]] + ranks[i]] = (uint32_t)i;
 }
 
-// Compaction: record k of every dst array <- record ord[k] of its src array,
-// then ord[k] = k.  All words are loaded before any is stored: interleaved, each
-// load would wait for the store before it (the record arrays are not known to
-// be disjoint), one memory round trip per word.
-__global__ void __launch_bounds__(kBlock)
-k_compact(uint32_t* __restrict__ ord, long P, Records rec) {
-    const long k = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (k >= P) return;
-    const long i = ord[k];
-    uint32_t buf[6][3];
-#pragma unroll
-    for (int a = 0; a < 6; ++a) {
-        if (a < rec.n) {
-            const int w = rec.words[a];
-            const uint32_t* src = rec.src[a] + i * w;
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                if (j < w) buf[a][j] = src[j];
-        }
-    }
-#pragma unroll
-    for (int a = 0; a < 6; ++a) {
-        if (a < rec.n) {
-            const int w = rec.words[a];
-            uint32_t* dst = rec.dst[a] + k * w;
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                if (j < w) dst[j] = buf[a][j];
-        }
-    }
-    ord[k] = (uint32_t)k;
-}
-
 // Words per particle of the record sets the sorts move: positions, momenta,
 // ids, then (with the cotangents) xi and pi.
 constexpr int kSortWords[5] = {3, 3, 1, 3, 3};
 
-// k_compact for the first N arrays of that layout: with the word counts fixed
-// at compile time, every gather load of a particle is issued before the first
-// wait (the branches on the run-time layout make k_compact wait once per array).
+// Compaction of the first N arrays of that layout: record k of every dst array
+// <- record ord[k] of its src array, then ord[k] = k.  With the word counts
+// fixed at compile time every gather load of a particle is issued before the
+// first wait and before any store (a load after a store to an array the
+// compiler cannot prove disjoint waits for the store; a branch on a run-time
+// layout waits for the loads in it).
 template <int N>
 __global__ void __launch_bounds__(kBlock)
 k_compact_sorted(uint32_t* __restrict__ ord, long P, Records rec) {
@@ -1371,16 +1341,16 @@ void launch_bin(const uint32_t* xq, const Lattice& L, Bins& b, bool counted, hip
                        b.keys, b.ranks, b.offsets, P, b.ord);
 }
 
-void launch_compact(Bins& b, const Records& rec, long P, hipStream_t s) {
-    const dim3 grid((unsigned)((P + kBlock - 1) / kBlock));
+bool launch_compact(Bins& b, const Records& rec, long P, hipStream_t s) {
     bool sorted_layout = rec.n == 3 || rec.n == 5;
     for (int a = 0; a < rec.n && sorted_layout; ++a) sorted_layout = rec.words[a] == kSortWords[a];
-    if (sorted_layout && rec.n == 3)
+    if (!sorted_layout) return false;
+    const dim3 grid((unsigned)((P + kBlock - 1) / kBlock));
+    if (rec.n == 3)
         hipLaunchKernelGGL(k_compact_sorted<3>, grid, dim3(kBlock), 0, s, b.ord, P, rec);
-    else if (sorted_layout)
-        hipLaunchKernelGGL(k_compact_sorted<5>, grid, dim3(kBlock), 0, s, b.ord, P, rec);
     else
-        hipLaunchKernelGGL(k_compact, grid, dim3(kBlock), 0, s, b.ord, P, rec);
+        hipLaunchKernelGGL(k_compact_sorted<5>, grid, dim3(kBlock), 0, s, b.ord, P, rec);
+    return true;
 }
 
 template <bool VEC>

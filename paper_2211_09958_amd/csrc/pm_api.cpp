@@ -408,7 +408,9 @@ double sort_particles(pm_ctx* ctx, bool cotangents) {
         rec.add(ctx->xi, ctx->xi_alt, 3);
         rec.add(ctx->pi, ctx->pi_alt, 3);
     }
-    launch_compact(ctx->bins, rec, ctx->P, ctx->stream);
+    // (the set above is the one launch_compact moves; were it refused, the
+    // records would stay where they are and the order would still hold)
+    if (!launch_compact(ctx->bins, rec, ctx->P, ctx->stream)) return bytes;
     std::swap(ctx->xq, ctx->xq_alt);
     std::swap(ctx->pq, ctx->pq_alt);
     std::swap(ctx->id, ctx->id_alt);
