@@ -51,6 +51,12 @@ struct Cfg {
     // two work-groups fit on a CU for the large transforms)
     static constexpr int MINW = H >= 512 ? 4 : 1;
     static constexpr int ROWS = T >= 256 ? 1 : 256 / T;   // rows per work-group, last axis
+    // columns per work-group for the axis-1 split pass: with two output
+    // streams, half-written 128-byte lines leave L2 before the neighbouring tile
+    // writes their other half (writes 1.24x the bytes at 8 columns), so the
+    // 1024-point split takes 16 columns, full lines (one 1024-thread
+    // work-group per CU, as the LDS holds one)
+    static constexpr int WY = H >= 1024 ? 16 : W;
 };
 
 // ---------------------------------------------------------- last axis
@@ -188,10 +194,10 @@ __device__ __forceinline__ int signed_freq(int p, int n) { return p < n / 2 ? p 
 // between); the stage twiddles come from an LDS copy, which leaves the
 // registers for it.
 template <int H>
-__global__ void __launch_bounds__(Cfg<H>::T * Cfg<H>::W, Cfg<H>::MINW)
+__global__ void __launch_bounds__(Cfg<H>::T * Cfg<H>::WY, Cfg<H>::MINW)
 k_fft_y_split(float2* __restrict__ g, float2* __restrict__ out_g, int cs, int ncb,
               const float2* __restrict__ tw, int ntw, const float2* __restrict__ st) {
-    constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::W;
+    constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::WY;
     // exchange buffer | the H-point part of the stage-twiddle table (H - 1 entries)
     __shared__ float2 lds[lds_slots(H) * W + H];
     float2* tab = lds + lds_slots(H) * W;
@@ -707,7 +713,7 @@ void launch_fft_y_split(float2* g, float2* out_g, int n, int cs, const Twiddles&
                         hipStream_t s) {
     size_switch(n, [&](auto nn) {
         constexpr int N = decltype(nn)::value;
-        constexpr int W = Cfg<N>::W, T = Cfg<N>::T;
+        constexpr int W = Cfg<N>::WY, T = Cfg<N>::T;
         const int ncb = cs / W;
         hipLaunchKernelGGL(k_fft_y_split<N>, dim3(N * ncb), dim3(T * W), 0, s, g, out_g, cs, ncb,
                            tw.w, tw.n, tw.stages);
