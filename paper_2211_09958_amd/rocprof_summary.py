@@ -94,7 +94,7 @@ def family(sym: str, ng: int):
         # and rank (8 bytes) for the next sort
         return {"0": ("gather", "56P+3r"), "1": ("gather", "24P+3r"),
                 "2": ("unkick_vjp", "72P+3r"), "3": ("wgrad", "92P+r")}.get(mode, (None, None))
-    if base in ("k_bin_count", "k_scan_local", "k_scan_bsum", "k_scan_add", "k_index", "k_compact",
+    if base in ("k_bin_count", "k_scan_local", "k_scan_bsum", "k_scan_add", "k_index",
                 "k_compact_sorted"):
         return "bin", None
     if base.startswith("k_mlp") or base == "k_adam":
