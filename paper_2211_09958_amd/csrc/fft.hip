@@ -304,12 +304,12 @@ k_grad_z(const float2* __restrict__ src, float2* __restrict__ dst, long dstStrid
 //
 // Vector-memory operations of a wave complete in issue order, so a wait for a
 // load also waits for every load and store issued before it.  The loop is
-// arranged so that the only such wait is the one at the top of a tile, for the
-// prefetched column, which the stores of the previous tile (issued after it)
-// do not delay: the stage twiddles are read from an LDS copy, the radial
-// multipliers come with the prefetch, and the prefetch is unconditional (the
-// last tile reloads itself) so that every path into the loop header leaves the
-// same operations in flight.
+// arranged so that it waits only for the prefetched column and multipliers,
+// issued a tile earlier, and never for loads issued just before the wait: the
+// stage twiddles are read from an LDS copy, the radial multipliers come with
+// the prefetch, and the prefetch is unconditional (the last tile reloads
+// itself) so that every path into the loop header leaves the same operations
+// in flight.
 //
 // The radial multiplier is a table lookup at |n|^2, which scatters a tile's
 // lookups over the whole table (one cache line per lookup, nearly); modes n0

@@ -44,14 +44,25 @@ FAMILY_SOURCES = {"fft_x": FFT_SOURCES, "fft_strided": FFT_SOURCES, "grad_z": FF
                   "bin": PARTICLE_SOURCES}
 
 
+# C/C++ comments, and the string and character literals that may contain comment markers
+_CODE_TOKENS = re.compile(r'//[^\n]*|/\*.*?\*/|"(?:\\.|[^"\\\n])*"|\'(?:\\.|[^\'\\\n])*\'', re.S)
+
+
+def code_only(text: str) -> str:
+    """Source text without comments and blank lines, trailing blanks stripped: what the
+    compiler sees, for deciding whether kernels changed."""
+    text = _CODE_TOKENS.sub(lambda m: "" if m.group(0).startswith("/") else m.group(0), text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def sources_sha256(family: str) -> str:
-    """Hash of the kernel sources (kernels and their launchers) of a family; its counter
-    figures go stale when it changes."""
+    """Hash of the kernel sources (kernels and their launchers) of a family, comments and
+    blank lines left out; its counter figures go stale when it changes."""
     h = hashlib.sha256()
     for name in FAMILY_SOURCES[family]:
         h.update(name.encode())
-        with open(os.path.join(HERE, "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(HERE, "csrc", name), encoding="utf-8") as f:
+            h.update(code_only(f.read()).encode())
     return h.hexdigest()
 
 

@@ -59,3 +59,14 @@ def test_window_calibration_and_ratio(tmp_path):
     assert t["families"]["fft_x"]["dispatches"] == 2
     md = (out / "kernel-trace_all-kernels_t.md").read_text()
     assert "| fft_x | 2 | 0.00 |" in md    # 800 ns over the two timed dispatches
+
+
+def test_source_hash_ignores_comments_only():
+    """Counter figures stay valid across comment edits, not across code edits."""
+    base = "__global__ void k(float* p) {  // doubles\n    p[0] *= 2.f;  /* in place */\n}\n"
+    reworded = "// a kernel\n__global__ void k(float* p) {  // twice the value\n\n    p[0] *= 2.f;\n}\n"
+    changed = "__global__ void k(float* p) {\n    p[0] *= 3.f;\n}\n"
+    quoted = 'const char* s = "a // b"; char c = \'/\';'
+    assert rs.code_only(base) == rs.code_only(reworded)
+    assert rs.code_only(base) != rs.code_only(changed)
+    assert rs.code_only(quoted) == quoted
