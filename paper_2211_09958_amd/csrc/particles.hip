@@ -583,12 +583,22 @@ k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, 
     }
 }
 
-// max |v| over n floats as float bits (non-negative floats order like their bits)
+// max |v| over n floats as float bits (non-negative floats order like their bits);
+// 16-byte loads when v is 16-byte aligned (the maximum does not depend on the order)
 __global__ void __launch_bounds__(kBlock)
 k_absmax(const float* __restrict__ v, long n, unsigned* __restrict__ out) {
     float m = 0.f;
-    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock)
-        m = fmaxf(m, fabsf(v[i]));
+    const long first = (long)blockIdx.x * kBlock + threadIdx.x, stride = (long)gridDim.x * kBlock;
+    long done = 0;
+    if ((reinterpret_cast<uintptr_t>(v) & 15) == 0) {
+        const float4* q = reinterpret_cast<const float4*>(v);
+        done = 4 * (n / 4);
+        for (long i = first; i < n / 4; i += stride) {
+            const float4 x = q[i];
+            m = fmaxf(m, fmaxf(fmaxf(fabsf(x.x), fabsf(x.y)), fmaxf(fabsf(x.z), fabsf(x.w))));
+        }
+    }
+    for (long i = done + first; i < n; i += stride) m = fmaxf(m, fabsf(v[i]));
     block_max_to(m, out);
 }
 
@@ -941,8 +951,18 @@ k_dot3(const float* __restrict__ a, const float* __restrict__ b, long P, double*
 __global__ void __launch_bounds__(1024)
 k_reduce(const double* __restrict__ partials, int n, double* __restrict__ sums, int slot) {
     __shared__ double red[16];
-    double v = 0.0;
-    for (int i = threadIdx.x; i < n; i += 1024) v += partials[i];
+    // four independent running sums per thread (a fixed order, so the result
+    // repeats bit for bit), so that four loads are in flight instead of one
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    int i = threadIdx.x;
+    for (; i + 3 * 1024 < n; i += 4 * 1024) {
+        v0 += partials[i];
+        v1 += partials[i + 1024];
+        v2 += partials[i + 2 * 1024];
+        v3 += partials[i + 3 * 1024];
+    }
+    for (; i < n; i += 1024) v0 += partials[i];
+    double v = (v0 + v1) + (v2 + v3);
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
