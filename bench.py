@@ -33,7 +33,7 @@ SCHEDULE = os.path.join(ROOT, "paper_2211_09958_amd", "weights",
 JOINT = (os.path.join(ROOT, "paper_2211_09958_amd", "weights", "joint_filter_128p_128m_63s_to_256m.npy"),
          os.path.join(ROOT, "paper_2211_09958_amd", "weights", "joint_schedule_128p_128m_63s_to_256m.npy"))
 FAMILY_KERNELS = {
-    "fft_strided": ["k_fft_strided", "k_fft_y_split"], "fft_x": ["k_fft_x_r2c", "k_fft_x_c2r"],
+    "fft_strided": ["k_fft_strided", "k_fft_y_split", "k_fft_y_merge"], "fft_x": ["k_fft_x_r2c", "k_fft_x_c2r"],
     "grad_z": ["k_grad_z"], "grad_adj_z": ["k_grad_adj_z"],
     "scatter": ["k_scatter_tile<16, false>"], "scatter_vec": ["k_scatter_tile<16, true>"],
     "gather": ["k_gather_tile<16, 0>"], "unkick_vjp": ["k_gather_tile<16, 2>"],

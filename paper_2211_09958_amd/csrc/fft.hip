@@ -231,6 +231,57 @@ k_fft_y_split(float2* __restrict__ g, float2* __restrict__ out_g, int cs, int nc
     for (int e = 0; e < E; ++e) g[off(j + e * T)] = lds[lpad(j + e * T) * W + c];
 }
 
+// Forward axis-1 pass of the transposed gradient that merges the axis-1 and
+// axis-2 terms: g1 <- n1 FFT_1(g1) + n2 FFT_1(g2), with n1 the axis-1 frequency
+// of the output row (zero on its Nyquist plane) and n2 = k2 the column's
+// (zero on its Nyquist column).  Both factors are known once the axis-1
+// transform is done and stay fixed along axis 0, so the axis-0 pass reads this
+// one spectrum in place of two.  The g1 column's transform is held in
+// registers while g2's is taken; the g2 column is loaded with g1's, and the
+// stage twiddles come from an LDS copy (as in k_fft_y_split).
+template <int H>
+__global__ void __launch_bounds__(Cfg<H>::T * Cfg<H>::WY, Cfg<H>::MINW)
+k_fft_y_merge(float2* __restrict__ g1, const float2* __restrict__ g2, int cs, int ncb,
+              const float2* __restrict__ st) {
+    constexpr int E = Cfg<H>::E, T = Cfg<H>::T, W = Cfg<H>::WY;
+    __shared__ float2 lds[lds_slots(H) * W + H];
+    float2* tab = lds + lds_slots(H) * W;
+    // read first in the second stage, after the first stage's barrier
+    for (int i = threadIdx.x; i < H - 1; i += T * W) tab[i] = st[H + i];
+    const int c = threadIdx.x % W, j = threadIdx.x / W;
+    const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int a = tile / ncb, cb = tile % ncb;   // a: axis-0 index
+    const int k2 = cb * W + c;
+    const float f2 = k2 == H / 2 ? 0.f : (float)k2;
+    auto off = [&](int p) -> long { return mesh_row(a, p, H) * cs + k2; };
+    float2 x[E], v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        v[e] = g1[off(j + e * T)];
+        x[e] = g2[off(j + e * T)];
+    }
+    fft_lds_tab<H, E, -1>(v, lds, W, c, j, tab);
+    __syncthreads();
+    float2 h[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = j + e * T;
+        const float f1 = p == H / 2 ? 0.f : (float)signed_freq(p, H);
+        const float2 y = lds[lpad(p) * W + c];
+        h[e] = make_float2(f1 * y.x, f1 * y.y);
+        v[e] = x[e];
+    }
+    __syncthreads();   // every lane has read the first transform's output
+    fft_lds_tab<H, E, -1>(v, lds, W, c, j, tab);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = j + e * T;
+        const float2 y = lds[lpad(p) * W + c];
+        g1[off(p)] = make_float2(h[e].x + f2 * y.x, h[e].y + f2 * y.y);
+    }
+}
+
 // Axis-0 pass with the fused gradient multiply (see launch_grad_z).  Writes
 // F~_0 = IFFT_0(i n0 radial delta) and G = IFFT_0(radial delta); F~_1 and F~_2
 // are i n1 G and i n2 G, and since n1 and n2 are constant along axis 0 those
@@ -429,8 +480,9 @@ k_grad_z_pipe(const float2* __restrict__ src, float2* __restrict__ dst, long dst
 
 // Axis-0 pass of the transposed gradient operator (see launch_grad_adj_z).
 // Sum_j conj(i n_j R) G_j = -i R (n0 G_0 + n1 G_1 + n2 G_2); n1 and n2 are fixed
-// along the column, so n1 G_1 + n2 G_2 is combined before its forward FFT:
-// three column FFTs per tile (four with the filter cotangent).
+// along the column, so n1 G_1 + n2 G_2 comes combined from the axis-1 pass
+// (k_fft_y_merge) as the second input spectrum: three column FFTs per tile
+// (four with the filter cotangent).
 template <int H, bool FILT>
 __global__ void __launch_bounds__(Cfg<H>::T * Cfg<H>::W)
 k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
@@ -452,8 +504,6 @@ k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
     auto off = [&](int p) -> long { return mesh_row(p, i1, n) * cs + k2; };
     const int n1 = signed_freq(i1, n);
     const bool in_half = k2 <= n / 2;
-    const float f1 = n1 == -n / 2 ? 0.f : (float)n1;
-    const float f2 = k2 == n / 2 ? 0.f : (float)k2;
     float2 v[E], a[E];
     // forward FFT of G_0, kept as n0 G_0 (zero on its Nyquist plane)
 #pragma unroll
@@ -467,16 +517,11 @@ k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
         const float2 g = lds[lpad(j + e * T) * W + c];
         a[e] = make_float2(f0 * g.x, f0 * g.y);
     }
-    // forward FFT of n1 G_1 + n2 G_2, added
+    // forward FFT of n1 G_1 + n2 G_2 (the second input spectrum), added
     {
-        const float2* g1 = src + srcStride;
-        const float2* g2 = src + 2 * srcStride;
+        const float2* u = src + srcStride;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const long o = off(j + e * T);
-            const float2 x = g1[o], y = g2[o];
-            v[e] = make_float2(f1 * x.x + f2 * y.x, f1 * x.y + f2 * y.y);
-        }
+        for (int e = 0; e < E; ++e) v[e] = u[off(j + e * T)];
     }
     __syncthreads();
     fft_lds_tab<H, E, -1>(v, lds, W, c, j, tab);
@@ -541,8 +586,8 @@ k_grad_adj_z(const float2* __restrict__ src, long srcStride, float2* dst,
 
 // k_grad_adj_z (without the filter cotangent) for the largest transforms, as a
 // persistent loop over tiles like k_grad_z_pipe: the tile's radial lookups and
-// its G_0, G_1 and G_2 columns are loaded at the top of the tile, and the sum
-// n0 G_0 + n1 G_1 + n2 G_2 of the forward transforms is kept in LDS.  As in
+// its G_0 and n1 G_1 + n2 G_2 columns are loaded at the top of the tile, and the
+// sum n0 G_0 + n1 G_1 + n2 G_2 of the forward transforms is kept in LDS.  As in
 // k_grad_z_pipe, each lane looks up the radial multipliers of |n0| <= H/2 only
 // and shares them through LDS, and the columns stream with non-temporal loads
 // and stores.
@@ -574,29 +619,23 @@ k_grad_adj_z_pipe(const float2* __restrict__ src, long srcStride, float2* dst, i
     auto at = [](const float2* base, long e_off, uint32_t lane) -> const float2* {
         return reinterpret_cast<const float2*>(reinterpret_cast<const char*>(base + e_off) + lane);
     };
-    const float2* g1 = src + srcStride;
-    const float2* g2 = src + 2 * srcStride;
+    const float2* u = src + srcStride;   // n1 G_1 + n2 G_2
     for (int tile = lw; tile < ntiles; tile += nwg) {
         const int i1 = tile / ncb, k2 = (tile % ncb) * W + c;
         const uint32_t lo = lane_off(tile);
         const int n1 = signed_freq(i1, n);
         const bool in_half = k2 <= n / 2;
-        const float f1 = n1 == -n / 2 ? 0.f : (float)n1;
-        const float f2 = k2 == n / 2 ? 0.f : (float)k2;
         float nr[EQ];
 #pragma unroll
         for (int e = 0; e < EQ; ++e) {
             const int q = e < EQ - 1 ? j + e * T : n / 2;
             nr[e] = radial[in_half ? q * q + n1 * n1 + k2 * k2 : 0];
         }
-        float2 v[E], y1[E], y2[E];
+        float2 v[E], y[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = ld_nt(at(src, e * estride, lo));
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            y1[e] = ld_nt(at(g1, e * estride, lo));
-            y2[e] = ld_nt(at(g2, e * estride, lo));
-        }
+        for (int e = 0; e < E; ++e) y[e] = ld_nt(at(u, e * estride, lo));
         // rq is free: the previous tile read it before its last transform
 #pragma unroll
         for (int e = 0; e < EQ - 1; ++e) rq[(j + e * T) * W + c] = in_half ? nr[e] : 0.f;
@@ -617,8 +656,7 @@ k_grad_adj_z_pipe(const float2* __restrict__ src, long srcStride, float2* dst, i
         }
         // forward FFT of n1 G_1 + n2 G_2, added to the kept column
 #pragma unroll
-        for (int e = 0; e < E; ++e)
-            v[e] = make_float2(f1 * y1[e].x + f2 * y2[e].x, f1 * y1[e].y + f2 * y2[e].y);
+        for (int e = 0; e < E; ++e) v[e] = y[e];
         __syncthreads();
         fft_lds_tab<H, E, -1>(v, lds, W, c, j, twl);
         __syncthreads();
@@ -717,6 +755,17 @@ void launch_fft_y_split(float2* g, float2* out_g, int n, int cs, const Twiddles&
         const int ncb = cs / W;
         hipLaunchKernelGGL(k_fft_y_split<N>, dim3(N * ncb), dim3(T * W), 0, s, g, out_g, cs, ncb,
                            tw.w, tw.n, tw.stages);
+    });
+}
+
+void launch_fft_y_merge(float2* g1, const float2* g2, int n, int cs, const Twiddles& tw,
+                        hipStream_t s) {
+    size_switch(n, [&](auto nn) {
+        constexpr int N = decltype(nn)::value;
+        constexpr int W = Cfg<N>::WY, T = Cfg<N>::T;
+        const int ncb = cs / W;
+        hipLaunchKernelGGL(k_fft_y_merge<N>, dim3(N * ncb), dim3(T * W), 0, s, g1, g2, cs, ncb,
+                           tw.stages);
     });
 }
 

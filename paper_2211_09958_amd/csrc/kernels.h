@@ -38,6 +38,11 @@ void launch_fft_x_c2r_dk2(float2* buf, int n, int cs, int nbuf, long bufStride, 
 // inverse axis-1 pass of G: out_g = IFFT_1(G), g <- IFFT_1(i n1 G)
 void launch_fft_y_split(float2* g, float2* out_g, int n, int cs, const Twiddles& tw,
                         hipStream_t s);
+// forward axis-1 pass merging two spectra: g1 <- n1 FFT_1(g1) + k2 FFT_1(g2)
+// (n1 the axis-1 frequency, zero on its Nyquist plane; k2 zero on the Nyquist
+// column): the input of launch_grad_adj_z's second spectrum
+void launch_fft_y_merge(float2* g1, const float2* g2, int n, int cs, const Twiddles& tw,
+                        hipStream_t s);
 // Complex transform along axis 0 or 1, in place; dir = -1 forward, +1 inverse.
 void launch_fft_axis(float2* buf, int n, int cs, int axis, int dir, int nbuf, long bufStride,
                      const Twiddles& tw, hipStream_t s);
@@ -49,8 +54,10 @@ void launch_fft_axis(float2* buf, int n, int cs, int axis, int dir, int nbuf, lo
 void launch_grad_z(const float2* src, float2* dst, long dstStride, int n, int cs,
                    const float* radial, const Twiddles& tw, hipStream_t s);
 // Fused axis-0 pass of the transpose: dst = inverse-axis-0 of
-// Sum_j conj(M_j) forward-axis-0(src + j*srcStride).  dst may equal the
-// `dens` buffer.  When fbar != nullptr also accumulates
+// Sum_j conj(M_j) forward-axis-0(G_j), with M_j = i n_j radial, given G_0 at src
+// and n1 G_1 + n2 G_2 (from launch_fft_y_merge) at src + srcStride, both
+// already transformed along axes 2 and 1.  dst may equal the `dens` buffer.
+// When fbar != nullptr also accumulates
 // fbar[|n|^2] += mult * Sum_j Re(conj(G_j) i n_j fscale/|n|^2 dens_k)
 // (mult = 1 on the k2 = 0, n/2 planes, else 2) using forward-axis-0(dens).
 void launch_grad_adj_z(const float2* src, long srcStride, float2* dst, const float2* dens,

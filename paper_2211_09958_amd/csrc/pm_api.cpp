@@ -468,15 +468,18 @@ void vjp_mesh(pm_ctx* ctx, const uint32_t* xq, const float* v, float coeff, doub
       launch_scatter_vec(xq, v, coeff, ctx->maxbits + kExtraSlots - 1, ctx->lat, ctx->bins,
                          ctx->creal(1), ctx->creal_stride(), s); }
     { KTimer t(ctx, PM_K_FFT_X, 3 * (r + c)); launch_fft_x_r2c(ctx->C[1], ng, cs, 3, cst, ctx->twd, s); }
-    { KTimer t(ctx, PM_K_FFT_STRIDED, 6 * c);
-      launch_fft_axis(ctx->C[1], ng, cs, 1, -1, 3, cst, ctx->twd, s); }
+    { KTimer t(ctx, PM_K_FFT_STRIDED, 2 * c);
+      launch_fft_axis(ctx->C[1], ng, cs, 1, -1, 1, cst, ctx->twd, s); }
+    // n1 G_1 + n2 G_2 into C2, the transposed axis-0 pass's second spectrum
+    { KTimer t(ctx, PM_K_FFT_STRIDED, 3 * c);
+      launch_fft_y_merge(ctx->C[2], ctx->C[3], ng, cs, ctx->twd, s); }
     float* fbar = nullptr;
     const float fscale = (float)(ctx->cfg.box / (2.0 * kPi) / std::pow((double)ng, 3.0));
     if (ctx->cfg.filter) {
         fbar = ctx->fbar;
         launch_zero(fbar, ctx->plan.ntab_f * sizeof(float), s);
     }
-    { KTimer t(ctx, PM_K_GRAD_ADJ_Z, (fbar ? 5 : 4) * c);
+    { KTimer t(ctx, PM_K_GRAD_ADJ_Z, (fbar ? 4 : 3) * c);
       launch_grad_adj_z(ctx->C[1], cst, ctx->C[0], ctx->C[0], ng, cs, ctx->radial_f, fbar, fscale,
                         ctx->twd, s); }
     if (ctx->cfg.filter) {
@@ -513,7 +516,8 @@ void grad_transpose(pm_ctx* ctx, const float* v, const float* radial) {
     const long rp = 2L * cs;
     launch_deinterleave(v, ctx->creal(1), ctx->creal_stride(), np, rp, s);
     launch_fft_x_r2c(ctx->C[1], np, cs, 3, cst, ctx->twd, s);
-    launch_fft_axis(ctx->C[1], np, cs, 1, -1, 3, cst, ctx->twd, s);
+    launch_fft_axis(ctx->C[1], np, cs, 1, -1, 1, cst, ctx->twd, s);
+    launch_fft_y_merge(ctx->C[2], ctx->C[3], np, cs, ctx->twd, s);
     launch_grad_adj_z(ctx->C[1], cst, ctx->C[0], ctx->C[0], np, cs, radial, nullptr, 0.f,
                       ctx->twd, s);
     launch_fft_axis(ctx->C[0], np, cs, 1, 1, 1, cst, ctx->twd, s);

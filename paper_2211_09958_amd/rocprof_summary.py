@@ -91,12 +91,12 @@ def family(sym: str, ng: int):
         return "fft_x", "rc_per_buf"
     if base == "k_fft_strided" and targs[:1] == [str(ng)]:
         return "fft_strided", "2c_per_buf"
-    if base == "k_fft_y_split" and targs[:1] == [str(ng)]:
+    if base in ("k_fft_y_split", "k_fft_y_merge") and targs[:1] == [str(ng)]:
         return "fft_strided", "3c"
     if base in ("k_grad_z", "k_grad_z_pipe") and targs[:1] == [str(ng)]:
         return "grad_z", "3c"
     if base in ("k_grad_adj_z", "k_grad_adj_z_pipe") and targs[:1] == [str(ng)]:
-        return "grad_adj_z", "5c" if targs[1:] == ["true"] else "4c"
+        return "grad_adj_z", "4c" if targs[1:] == ["true"] else "3c"
     if base == "k_scatter_tile":
         return ("scatter_vec", "24P+3r") if targs[1:] == ["true"] else ("scatter", "12P+r")
     if base == "k_gather_tile":
