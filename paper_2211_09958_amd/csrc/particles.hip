@@ -512,10 +512,17 @@ k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, 
     ulonglong2* acc2 = reinterpret_cast<ulonglong2*>(acc);
     float kw[8], kv[3];   // VEC: the kept first particle
     uint32_t kcell[4];
+    // the accumulator starts at zero; each component's write-out clears the
+    // slots it reads for the next one
+    for (int c = threadIdx.x; c < T3 / 2; c += NTH) acc2[c] = make_ulonglong2(0ull, 0ull);
+    __syncthreads();
+    // cell value v * 2^-e (minus the mean density 1 for the density), formed
+    // from v's 32-bit halves with one rounding: hi 2^(32-e) + lo 2^-e exactly,
+    // as the double conversion of v scaled by 2^-e (exact for |v| < 2^53, and
+    // the same rounding of v beyond, since scaling by 2^-e commutes with it)
+    const double hi_scale = inv_scale * 4294967296.0;
 #pragma unroll
     for (int comp = 0; comp < NC; ++comp) {
-        for (int c = threadIdx.x; c < T3 / 2; c += NTH) acc2[c] = make_ulonglong2(0ull, 0ull);
-        __syncthreads();
         // one flat index space over the 20 ranges, so every lane has work.  A
         // particle's storage slot is loaded two iterations ahead and its record
         // one iteration ahead, so neither load is waited for before the atomics
@@ -570,12 +577,18 @@ k_scatter_tile(const uint32_t* __restrict__ xq, const float* __restrict__ vals, 
             const long g = mesh_row(lo[0] + l0, lo[1] + l1, L.ng) * L.rp + lo[2] + l2;
             const int sl = tile_slot<T>(l0, l1, l2);   // four consecutive slots
             const ulonglong2 a = acc2[sl / 2], b = acc2[sl / 2 + 1];
+            if (comp + 1 < NC) {
+                acc2[sl / 2] = make_ulonglong2(0ull, 0ull);
+                acc2[sl / 2 + 1] = make_ulonglong2(0ull, 0ull);
+            }
             const unsigned long long v4[4] = {a.x, a.y, b.x, b.y};
             float r4[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const double v = (double)(long long)v4[i] * inv_scale;
-                r4[i] = VEC ? (float)v : (float)(v - 1.0);
+                // the density's unit is 2^-32 (e = 32): minus 1 is minus 1 from hi
+                const int hi = (int)(v4[i] >> 32) - (VEC ? 0 : 1);
+                const unsigned lo = (unsigned)v4[i];
+                r4[i] = (float)fma((double)lo, inv_scale, (double)hi * hi_scale);
             }
             *reinterpret_cast<float4*>(o + g) = make_float4(r4[0], r4[1], r4[2], r4[3]);
         }
